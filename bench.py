@@ -1,0 +1,210 @@
+"""Benchmark: bins x (NLL + gradient) per second on one MI355X.
+
+Workload: a 1D histogram of 1e7 bins on [0,100] with two Gaussian peaks
+(amplitudes 1e3..1e5, means in [10,90], widths 0.5..3) on a cubic
+background, Poisson counts; one step is one nll_grad call (NLL and the
+10-component reverse-mode gradient over every bin, FP64 accumulation).
+Eight distinct histograms (320 MB, more than the 256 MB last-level cache)
+are visited in turn so every step reads its counts from HBM.
+
+The K timed steps are replayed from a captured HIP graph (so host launch
+overhead stays out of the kernel timing) between HIP events recorded on the
+stream the kernels run on.  One JSON line is printed.
+
+The CPU baseline times the FP64 oracle (test infrastructure) on the host on
+one full histogram, repeated for ~10 s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NBINS = 10_000_000
+NCOPIES = 8
+HBM_PEAK_GBS = 8000.0
+FP64_VEC_PEAK_TFLOPS = 78.6
+
+# Algorithmic FP64 flops per bin of the timed workload (two Gaussians, cubic
+# background, Poisson objective, value + 10-component gradient), counting
+# +, -, * as one flop and a fused multiply-add as two; the elementary
+# functions are counted at the flops of a textbook FP64 evaluation
+# (exp: Cody-Waite reduction + degree-11 polynomial = 26; log: reduction +
+# degree-8 polynomial in s^2 with s = f/(2+f) = 30 including its division;
+# division: reciprocal + two Newton steps + residual correction = 10).
+FLOPS_BASIC = 49
+FLOPS_EXP, FLOPS_LOG, FLOPS_DIV = 26, 30, 10
+FLOPS_PER_BIN = FLOPS_BASIC + 2 * FLOPS_EXP + FLOPS_LOG + FLOPS_DIV
+BYTES_PER_BIN = 4  # one u32 count per bin
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(case, obj, seconds=10.0):
+    import oracle
+    spec = case["spec"]
+    m = oracle.Model(spec["kind"], spec["n_gauss"], spec["poly_degree"], spec["t_shift"],
+                     spec["t_scale"])
+    cores = cpu_cores()
+    reps, t0 = 0, time.perf_counter()
+    ref = None
+    while True:
+        ref = oracle.nll_grad(m, obj, case["counts"], case["theta_eval"], case["range"],
+                              nthreads=cores)
+        reps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return ref, dict(value=reps * NBINS / dt, unit="bins*(NLL+grad)/s", cores=cores,
+                     kind="oracle",
+                     sample="%d full passes over one 1e7-bin histogram in %.1f s, %d threads"
+                     % (reps, dt, cores))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--precision", choices=["fp64", "fp32bin"], default="fp64")
+    ap.add_argument("--objective", choices=["poisson", "neyman", "pearson"], default="poisson")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the histogram objective is not sharded across GPUs "
+              "in this build (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2203_06139_amd as hf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
+    prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
+
+    log("generating %d histograms of %d bins" % (NCOPIES, NBINS))
+    hists, thetas, cases = [], [], []
+    for k in range(NCOPIES):
+        c = datagen.large_fit_case(seed=20 + k, nbins=NBINS)
+        cases.append(c)
+        hists.append(hf.make_hist(c["counts"], c["range"], device=dev))
+        thetas.append(torch.as_tensor(c["theta_eval"], dtype=torch.float64, device=dev))
+    model = hf.Model.from_spec(cases[0]["spec"])
+    P = model.nparams
+    nll_out = [torch.empty(1, dtype=torch.float64, device=dev) for _ in range(NCOPIES)]
+    grad_out = [torch.empty(P, dtype=torch.float64, device=dev) for _ in range(NCOPIES)]
+
+    def step(k):
+        j = k % NCOPIES
+        hf.nll_grad(hists[j], model, thetas[j], objective=obj, precision=prec,
+                    nll_out=nll_out[j], grad_out=grad_out[j])
+
+    log("warmup %d" % args.warmup)
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+
+    per_graph = NCOPIES * 4
+    graph = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(graph, stream=s):
+                for k in range(per_graph):
+                    step(k)
+        torch.cuda.synchronize()
+        graph.replay()  # untimed replay
+        torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = args.steps
+    if graph is not None:
+        steps = max(per_graph, (steps + per_graph - 1) // per_graph * per_graph)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter()
+    ev0.record(stream)
+    if graph is not None:
+        for _ in range(steps // per_graph):
+            graph.replay()
+    else:
+        for k in range(steps):
+            step(k)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / steps
+    value = NBINS / (ms_per_step * 1e-3)
+    log("timed %d steps: %.3f ms total, %.2f us/step (host %.3f s)"
+        % (steps, ms, 1e3 * ms_per_step, t_host))
+
+    # parity of the timed configuration against the oracle on copy 0
+    result = dict(
+        metric="bins*(NLL+grad)/s",
+        value=value,
+        unit="bins/s",
+        n_gpus=1,
+        steps=steps,
+        warmup=args.warmup,
+        ms_per_step=ms_per_step,
+        higher_is_better=True,
+        scaling="weak",
+        vs_baseline=None,
+        dtype="f64" if prec == hf.FP64 else "f32-bin/f64-acc",
+        data="synthetic",
+        config=dict(workload="1D histogram, 1e7 bins on [0,100], two Gaussians + cubic "
+                             "background (10 parameters), %s NLL + reverse-mode gradient, "
+                             "%s bins, 8 rotating histograms" % (args.objective, args.precision),
+                    nbins=NBINS, params=P, objective=args.objective,
+                    precision=args.precision, graph=graph is not None),
+    )
+    flops = FLOPS_PER_BIN * NBINS
+    achieved = flops / (ms_per_step * 1e-3) / 1e12
+    result["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VEC_PEAK_TFLOPS,
+                              unit="TFLOP/s", frac=achieved / FP64_VEC_PEAK_TFLOPS, traffic=None,
+                              flops_per_bin=FLOPS_PER_BIN,
+                              hbm_gbs=BYTES_PER_BIN * NBINS / (ms_per_step * 1e-3) / 1e9,
+                              hbm_frac=BYTES_PER_BIN * NBINS / (ms_per_step * 1e-3) / 1e9 /
+                              HBM_PEAK_GBS)
+    torch.cuda.synchronize()
+    j0 = 0
+    g_nll = nll_out[j0].item()
+    g_grad = grad_out[j0].cpu().numpy()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        ref, cb = cpu_baseline(cases[j0], obj)
+        result["cpu_baseline"] = cb
+        tol = 1e-10 if prec == hf.FP64 else 1e-5
+        err_nll = abs(g_nll - ref.nll) / ref.scales[0]
+        err_grad = float(np.max(np.abs(g_grad - ref.grad) / ref.scales[1:]))
+        result["parity"] = dict(rel_err_nll=err_nll, rel_err_grad=err_grad, tol=tol,
+                                ok=bool(err_nll <= tol and err_grad <= tol))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

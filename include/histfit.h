@@ -1,0 +1,204 @@
+/*
+ * histfit.h -- C ABI of the MI355X (gfx950) histogram-fit library.
+ *
+ * The library evaluates a binned fit objective and its reverse-mode gradient
+ * with respect to the model parameters, and fits histograms with it.  This is
+ * the computation the paper accelerates with AD (sec. 4 "Integration and
+ * Results", Fig. 2a: a parametric function fitted to a uniformly binned
+ * histogram with an AD-generated gradient; sec. 2 "Background": reverse
+ * accumulation gives the gradient of a scalar objective at a cost independent
+ * of the number of parameters).  The gradient routine takes the inputs and
+ * caller-provided output adjoints for the selected parameters, as the
+ * generated gradient of Listing 1 (sec. 3) does.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Memory.   Every array argument is a DEVICE pointer on the context's GPU
+ *           unless stated otherwise.  The caller owns all inputs and outputs;
+ *           the library never frees caller memory.  Descriptor structs
+ *           (hf_hist, hf_model, hf_fit_opts) are read on the host during the
+ *           call and may be reused at once.
+ * Streams.  Work is enqueued on `stream` (a hipStream_t; NULL is the null
+ *           stream) and is asynchronous: outputs are valid once the stream has
+ *           been synchronised.  No call synchronises the stream.
+ * Returns.  0 on success or a negative hf_error code for what the host can
+ *           check (null pointers, sizes, dtypes, unsupported combinations,
+ *           HIP launch errors).  hf_last_error() gives the message.
+ * Status.   Data-dependent conditions never fail the call; they are written
+ *           to a device status word (bit field, hf_bin_status) so that no
+ *           call forces a host synchronisation:
+ *             HF_ST_DOMAIN     a bin had mu <= 0 where the objective needs
+ *                              mu > 0; the NLL is +inf and that bin adds
+ *                              nothing to the gradient;
+ *             HF_ST_NONFINITE  theta held a NaN or infinity.
+ * Threads.  A context is not thread safe and its calls must not overlap:
+ *           use one context per host thread or per concurrently used stream.
+ *           Calls serialised on one stream may share a context.
+ * Results.  Reductions run in a fixed order: repeated calls with the same
+ *           inputs on the same GPU give bit-identical outputs.
+ *
+ * Models (theta layout, all FP64)
+ * -------------------------------
+ *   HF_GAUSS_POLY  1D: sum over n_gauss Gaussians A exp(-((x-m)/s)^2/2),
+ *                  theta = (A,m,s) per Gaussian, then the polynomial
+ *                  background sum_{j=0..poly_degree} c_j t^j with
+ *                  t = (x - t_shift)/t_scale; poly_degree = -1: no background.
+ *                  The amplitude form matches the "gaus" function
+ *                  {Constant, Mean, Sigma} that Fig. 2a fits.
+ *   HF_GAUSS_EXP   1D: the same Gaussians plus exp(b0 + b1 t), theta ends
+ *                  with (b0, b1).
+ *   HF_GAUSS2D     2D: A exp(-Q/2) + c, Q = (u^2 - 2 rho u v + v^2)/(1-rho^2),
+ *                  u = (x-mx)/sx, v = (y-my)/sy;
+ *                  theta = (A, mx, my, sx, sy, rho, c).
+ * Supported sizes: 0 <= n_gauss <= 4 and -1 <= poly_degree <= 3 (at least
+ * one term), so P = hf_model_nparams() <= 16.
+ * The model is evaluated at bin centres x_i = lo + (i + 1/2)(hi - lo)/n.
+ *
+ * Objectives (per bin, count n, model mu, optional weight w; L = sum w l)
+ * -----------------------------------------------------------------------
+ *   HF_NEYMAN   l = (n - mu)^2 / n, bins with n = 0 skipped.
+ *   HF_PEARSON  l = (n - mu)^2 / mu.
+ *   HF_POISSON  l = mu - n + n ln(n/mu) (n > 0),  l = mu (n = 0): the
+ *               Poisson negative log-likelihood minus its saturated value
+ *               (no factor 2); same minimiser and gradient as
+ *               sum(mu - n ln mu).
+ *
+ * Precision
+ * ---------
+ *   HF_FP64      every per-bin step in FP64.
+ *   HF_FP32_BIN  the per-bin transcendental and reciprocal steps use FP32
+ *                hardware instructions (bin centres and x - m stay FP64);
+ *                NLL and gradient are accumulated in FP64 either way.
+ */
+#ifndef HISTFIT_H
+#define HISTFIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hf_stream_t; /* same type as hipStream_t */
+typedef struct hf_ctx hf_ctx;
+
+typedef enum {
+  HF_OK = 0,
+  HF_EINVAL = -1,       /* null pointer, bad size, dtype or parameter count */
+  HF_EUNSUPPORTED = -2, /* model/objective/precision combination not built */
+  HF_EHIP = -3,         /* a HIP runtime call failed                        */
+  HF_ENOMEM = -4,       /* device scratch could not be allocated            */
+  HF_ECAPTURE = -5      /* scratch would have to grow during stream capture */
+} hf_error;
+
+typedef enum { HF_NEYMAN = 0, HF_PEARSON = 1, HF_POISSON = 2 } hf_objective;
+typedef enum { HF_GAUSS_POLY = 1, HF_GAUSS_EXP = 2, HF_GAUSS2D = 3 } hf_model_kind;
+typedef enum { HF_FP64 = 0, HF_FP32_BIN = 1 } hf_precision;
+typedef enum { HF_U32 = 0, HF_F32 = 1, HF_F64 = 2 } hf_dtype;
+typedef enum { HF_ST_DOMAIN = 1, HF_ST_NONFINITE = 2 } hf_bin_status;
+
+typedef struct {
+  int32_t kind;        /* hf_model_kind                                   */
+  int32_t n_gauss;     /* 0..4 (HF_GAUSS2D: ignored)                      */
+  int32_t poly_degree; /* -1..3 (HF_GAUSS_POLY only)                      */
+  int32_t reserved;    /* must be 0                                       */
+  double t_shift;      /* background variable t = (x - t_shift)/t_scale   */
+  double t_scale;      /* nonzero                                         */
+} hf_model;
+
+typedef struct {
+  const void* counts;   /* device, nx*ny values of counts_dtype, row-major
+                           with x fastest; 16-byte aligned                 */
+  const float* weights; /* device f32[nx*ny] per-bin weights, or NULL (1);
+                           16-byte aligned                                 */
+  int64_t nx;           /* bins along x, >= 1                              */
+  int64_t ny;           /* bins along y; 1 for the 1D models               */
+  int32_t counts_dtype; /* hf_dtype                                        */
+  int32_t reserved;     /* must be 0                                       */
+  double xlo, xhi;      /* x range, xhi > xlo                              */
+  double ylo, yhi;      /* y range (2D only), yhi > ylo                    */
+} hf_hist;
+
+/* Creates a context on HIP device `device` and makes it current for the
+ * calling thread.  The context owns the device scratch used by reductions
+ * and fits (per-block partial sums, a completion ticket, fit work queue).
+ * Scratch grows on demand and is never freed before hf_ctx_destroy; a call
+ * that would grow it while `stream` is being captured returns HF_ECAPTURE
+ * (warm the context up with one uncaptured call of the same size first).  */
+int hf_ctx_create(hf_ctx** out, int device);
+void hf_ctx_destroy(hf_ctx* ctx);
+/* Message of the last failing call on ctx (empty string if none); valid
+ * until the next call on ctx.  ctx may be NULL for hf_ctx_create errors.  */
+const char* hf_last_error(const hf_ctx* ctx);
+
+/* Number of parameters P of a model, or HF_EINVAL / HF_EUNSUPPORTED.      */
+int hf_model_nparams(const hf_model* model);
+
+/* NLL value.
+ *   theta      device f64[P], read on the device (no host copy).
+ *   nll_out    device f64[1], overwritten with L(theta).
+ *   status_out device i32[1] or NULL, overwritten with the hf_bin_status
+ *              bits of this evaluation.                                   */
+int nll_eval(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t objective,
+             int32_t precision, const double* theta, double* nll_out, int32_t* status_out,
+             hf_stream_t stream);
+
+/* NLL and its reverse-mode gradient, in one pass over the bins.
+ *   seed       device f64[1] upstream adjoint dOut/dL, or NULL for 1.
+ *   nll_out    device f64[1], overwritten with L(theta) (not scaled by seed).
+ *   grad_out   device f64[P], OVERWRITTEN (not accumulated) with
+ *              seed * dL/dtheta; entries whose bit is clear in free_mask are
+ *              set to 0.  free_mask = 0 selects every parameter.
+ *   grad_w_out device f32[nx*ny] or NULL, 16-byte aligned: seed * dL/dw_i =
+ *              seed * l_i per bin (+inf for domain-error bins).
+ *   status_out as for nll_eval.                                           */
+int nll_grad(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t objective,
+             int32_t precision, const double* theta, const double* seed, double* nll_out,
+             double* grad_out, float* grad_w_out, uint32_t free_mask, int32_t* status_out,
+             hf_stream_t stream);
+
+/* Options of the fitter: BFGS on the inverse Hessian in scaled coordinates,
+ * backtracking Armijo line search (c1 = 1e-4, step halved up to ls_max
+ * times), stop when EDM = g^T H g / 2 < max(edm_tol, 4 eps |L|).         */
+typedef struct {
+  int32_t max_iter;    /* iteration limit, >= 1                           */
+  int32_t ls_max;      /* line-search halvings, 1..60                     */
+  int32_t fixed_iters; /* nonzero: ignore the EDM test (timing runs)      */
+  uint32_t free_mask;  /* bit k set: theta_k is fitted; 0 = all           */
+  double edm_tol;      /* convergence threshold on EDM                    */
+  double polish_edm;   /* HF_FP32_BIN: switch to FP64 bins once EDM is
+                          below this (<= 0: never switch)                 */
+} hf_fit_opts;
+
+/* Per-fit status codes written to status[b] by fit_batch.                */
+typedef enum {
+  HF_FIT_CONVERGED = 0,
+  HF_FIT_MAXITER = 1,
+  HF_FIT_LSFAIL = 2,
+  HF_FIT_NONFINITE = 3,
+  HF_FIT_DOMAIN = 4,
+  HF_FIT_BADHIST = 5 /* offsets[b+1] <= offsets[b] or a bad range        */
+} hf_fit_status;
+
+/* Fits B independent 1D histograms in one launch.
+ *   counts_concat device array of counts_dtype: histogram b occupies
+ *                 [offsets[b], offsets[b+1]).
+ *   offsets       device i64[B+1], offsets[0] = 0, nondecreasing.
+ *   ranges        device f64[2B]: (lo_b, hi_b).
+ *   theta0        device f64[B*P] start points; theta_out device f64[B*P]
+ *                 canonicalised results (|s|, Gaussians ordered by mean).
+ *   nll_out       device f64[B]: final L, re-evaluated with FP64 bins.
+ *   status, iters, nevals  device i32[B]: hf_fit_status, BFGS iterations,
+ *                 objective evaluations.
+ * Only HF_GAUSS_POLY and HF_GAUSS_EXP models.                             */
+int fit_batch(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t counts_dtype,
+              const int64_t* offsets, const double* ranges, const hf_model* model,
+              int32_t objective, int32_t precision, const double* theta0, const hf_fit_opts* opts,
+              double* theta_out, double* nll_out, int32_t* status, int32_t* iters,
+              int32_t* nevals, hf_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISTFIT_H */

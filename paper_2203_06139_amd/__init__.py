@@ -1,0 +1,309 @@
+"""MI355X histogram-fit library: Python binding of libhistfit.so.
+
+The binding only marshals arguments: torch tensors supply device memory and
+the current HIP stream, and every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/histfit.h.  There is no CPU
+fallback: if the library is missing or no GPU is visible, the calls raise.
+
+Calls (same names as the C ABI):
+  nll_eval(hist, model, theta, objective=POISSON, precision=FP64)
+  nll_grad(hist, model, theta, objective=POISSON, precision=FP64, seed=None,
+           want_grad_w=False, free_mask=0)
+  fit_batch(counts_concat, offsets, ranges, model, theta0, objective=POISSON,
+            precision=FP64, **fit options)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhistfit.so")
+
+NEYMAN, PEARSON, POISSON = 0, 1, 2
+GAUSS_POLY, GAUSS_EXP, GAUSS2D = 1, 2, 3
+FP64, FP32_BIN = 0, 1
+U32, F32, F64 = 0, 1, 2
+ST_DOMAIN, ST_NONFINITE = 1, 2
+FIT_CONVERGED, FIT_MAXITER, FIT_LSFAIL, FIT_NONFINITE, FIT_DOMAIN, FIT_BADHIST = range(6)
+
+
+class HfModel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_gauss", ctypes.c_int32),
+                ("poly_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_shift", ctypes.c_double), ("t_scale", ctypes.c_double)]
+
+
+class HfHist(ctypes.Structure):
+    _fields_ = [("counts", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("counts_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("xlo", ctypes.c_double), ("xhi", ctypes.c_double),
+                ("ylo", ctypes.c_double), ("yhi", ctypes.c_double)]
+
+
+class HfFitOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("ls_max", ctypes.c_int32),
+                ("fixed_iters", ctypes.c_int32), ("free_mask", ctypes.c_uint32),
+                ("edm_tol", ctypes.c_double), ("polish_edm", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class Model:
+    """Model descriptor (see include/histfit.h for the parameter layout)."""
+    kind: int
+    n_gauss: int = 1
+    poly_degree: int = -1
+    t_shift: float = 0.0
+    t_scale: float = 1.0
+
+    def c(self) -> HfModel:
+        return HfModel(self.kind, self.n_gauss, self.poly_degree, 0, float(self.t_shift),
+                       float(self.t_scale))
+
+    @staticmethod
+    def from_spec(spec: dict) -> "Model":
+        return Model(spec["kind"], spec.get("n_gauss", 1), spec.get("poly_degree", -1),
+                     spec.get("t_shift", 0.0), spec.get("t_scale", 1.0))
+
+    @property
+    def nparams(self) -> int:
+        rc = load().hf_model_nparams(ctypes.byref(self.c()))
+        if rc < 0:
+            raise ValueError("unsupported model %r" % (self,))
+        return rc
+
+
+class HistfitError(RuntimeError):
+    pass
+
+
+_lib = None
+_ctx = {}
+
+
+def load():
+    """Load libhistfit.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  -- binds libamdhip64 before our library
+    if not os.path.exists(LIB_PATH):
+        raise HistfitError("libhistfit.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64
+    L.hf_ctx_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+    L.hf_ctx_create.restype = ctypes.c_int
+    L.hf_ctx_destroy.argtypes = [vp]
+    L.hf_ctx_destroy.restype = None
+    L.hf_last_error.argtypes = [vp]
+    L.hf_last_error.restype = ctypes.c_char_p
+    L.hf_model_nparams.argtypes = [ctypes.POINTER(HfModel)]
+    L.hf_model_nparams.restype = ctypes.c_int
+    L.nll_eval.argtypes = [vp, ctypes.POINTER(HfHist), ctypes.POINTER(HfModel), i32, i32, vp, vp,
+                           vp, vp]
+    L.nll_eval.restype = ctypes.c_int
+    L.nll_grad.argtypes = [vp, ctypes.POINTER(HfHist), ctypes.POINTER(HfModel), i32, i32, vp, vp,
+                           vp, vp, vp, u32, vp, vp]
+    L.nll_grad.restype = ctypes.c_int
+    L.fit_batch.argtypes = [vp, i32, vp, i32, vp, vp, ctypes.POINTER(HfModel), i32, i32, vp,
+                            ctypes.POINTER(HfFitOpts), vp, vp, vp, vp, vp, vp]
+    L.fit_batch.restype = ctypes.c_int
+    _ = i64
+    _lib = L
+    return L
+
+
+def context(device: int | None = None):
+    """The library context of a device (created on first use, kept for the process)."""
+    import torch
+    L = load()
+    if not torch.cuda.is_available():
+        raise HistfitError("no GPU visible: the HIP library has no CPU path")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _ctx:
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            rc = L.hf_ctx_create(ctypes.byref(h), dev)
+        if rc != 0:
+            raise HistfitError("hf_ctx_create(%d) failed: %d" % (dev, rc))
+        _ctx[dev] = h
+    return _ctx[dev]
+
+
+def _check(rc, ctx):
+    if rc != 0:
+        raise HistfitError("histfit error %d: %s" % (rc, load().hf_last_error(ctx).decode()))
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.int32 or t.dtype == torch.uint32:
+        return U32
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("counts must be int32/uint32 (read as u32), float32 or float64")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_tensor(t, dtype, device, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t, dtype=dtype)
+    if t.device.type != "cuda":
+        t = t.to(device)
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    if not t.is_contiguous():
+        t = t.contiguous()
+    return t
+
+
+@dataclass
+class Hist:
+    """A histogram on the device: counts [nx] or [ny, nx] (x fastest)."""
+    counts: object
+    xrange: tuple
+    yrange: tuple = (0.0, 1.0)
+    weights: object = None
+
+    def c(self) -> HfHist:
+        c = self.counts
+        nx = c.shape[-1]
+        ny = c.shape[0] if c.dim() == 2 else 1
+        return HfHist(c.data_ptr(), self.weights.data_ptr() if self.weights is not None else None,
+                      nx, ny, _dtype_code(c), 0, float(self.xrange[0]), float(self.xrange[1]),
+                      float(self.yrange[0]), float(self.yrange[1]))
+
+
+def make_hist(counts, xrange, yrange=(0.0, 1.0), weights=None, device=None) -> Hist:
+    """Device copies (if needed) of counts and weights, contiguous."""
+    import numpy as np
+    import torch
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    if isinstance(counts, np.ndarray):
+        arr = np.ascontiguousarray(counts)
+        c = torch.from_numpy(arr.view(np.int32) if arr.dtype == np.uint32 else arr)
+    else:
+        c = counts
+    if c.dtype == torch.uint32:
+        c = c.view(torch.int32)
+    if c.dtype not in (torch.int32, torch.float32, torch.float64):
+        c = c.to(torch.float64)
+    c = c.to(device).contiguous()
+    w = None if weights is None else _dev_tensor(weights, torch.float32, device, "weights")
+    return Hist(c, tuple(xrange), tuple(yrange), w)
+
+
+def _check_theta(th, model):
+    P = model.nparams
+    if th.numel() != P:
+        raise ValueError("theta has %d values, the model has %d parameters" % (th.numel(), P))
+
+
+def _check_hist_sizes(hist: Hist):
+    c = hist.counts
+    if c.dim() not in (1, 2):
+        raise ValueError("counts must be [nx] or [ny, nx]")
+    if hist.weights is not None and hist.weights.numel() != c.numel():
+        raise ValueError("weights must have one value per bin")
+
+
+def nll_eval(hist: Hist, model: Model, theta, objective=POISSON, precision=FP64, out=None,
+             status=None):
+    """L(theta) as a device f64[1] tensor (and the status word if asked for)."""
+    import torch
+    dev = hist.counts.device
+    ctx = context(dev.index)
+    th = _dev_tensor(theta, torch.float64, dev, "theta")
+    _check_theta(th, model)
+    _check_hist_sizes(hist)
+    out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    rc = load().nll_eval(ctx, ctypes.byref(hist.c()), ctypes.byref(model.c()), objective,
+                         precision, _ptr(th), _ptr(out), _ptr(status), _stream(dev))
+    _check(rc, ctx)
+    return out
+
+
+def nll_grad(hist: Hist, model: Model, theta, objective=POISSON, precision=FP64, seed=None,
+             want_grad_w=False, free_mask=0, nll_out=None, grad_out=None, grad_w_out=None,
+             status=None):
+    """(L, dL/dtheta * seed, optional seed * dL/dw) as device tensors."""
+    import torch
+    dev = hist.counts.device
+    ctx = context(dev.index)
+    th = _dev_tensor(theta, torch.float64, dev, "theta")
+    _check_theta(th, model)
+    _check_hist_sizes(hist)
+    P = th.numel()
+    if grad_out is not None and grad_out.numel() < P:
+        raise ValueError("grad_out too small")
+    if grad_w_out is not None and grad_w_out.numel() != hist.counts.numel():
+        raise ValueError("grad_w_out must have one value per bin")
+    nll_out = torch.empty(1, dtype=torch.float64, device=dev) if nll_out is None else nll_out
+    grad_out = torch.empty(P, dtype=torch.float64, device=dev) if grad_out is None else grad_out
+    if want_grad_w and grad_w_out is None:
+        grad_w_out = torch.empty(hist.counts.shape, dtype=torch.float32, device=dev)
+    sd = None if seed is None else _dev_tensor(seed, torch.float64, dev, "seed")
+    rc = load().nll_grad(ctx, ctypes.byref(hist.c()), ctypes.byref(model.c()), objective,
+                         precision, _ptr(th), _ptr(sd), _ptr(nll_out), _ptr(grad_out),
+                         _ptr(grad_w_out), free_mask, _ptr(status), _stream(dev))
+    _check(rc, ctx)
+    return nll_out, grad_out, grad_w_out
+
+
+@dataclass
+class FitBatchResult:
+    theta: object
+    nll: object
+    status: object
+    iters: object
+    nevals: object
+
+
+def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=POISSON,
+              precision=FP64, max_iter=500, ls_max=30, fixed_iters=False, free_mask=0,
+              edm_tol=1e-10, polish_edm=0.0, out: FitBatchResult | None = None):
+    """Fit B histograms laid end to end in counts_concat; device tensors out."""
+    import torch
+    c = counts_concat
+    dev = c.device
+    ctx = context(dev.index)
+    if not isinstance(offsets, torch.Tensor) or offsets.device.type == "cpu":
+        # host-side check that every histogram lies inside counts_concat
+        import numpy as np
+        o = np.asarray(offsets.numpy() if isinstance(offsets, torch.Tensor) else offsets,
+                       dtype=np.int64)
+        if o.ndim != 1 or o.size < 1 or o[0] != 0 or np.any(np.diff(o) < 0) or o[-1] > c.numel():
+            raise ValueError("offsets must start at 0, be nondecreasing and end <= counts size")
+    off = _dev_tensor(offsets, torch.int64, dev, "offsets")
+    rg = _dev_tensor(ranges, torch.float64, dev, "ranges")
+    B = off.numel() - 1
+    P = model.nparams
+    th0 = _dev_tensor(theta0, torch.float64, dev, "theta0")
+    if th0.numel() != B * P or rg.numel() != 2 * B:
+        raise ValueError("theta0 must be [B, P] and ranges [B, 2]")
+    if out is None:
+        out = FitBatchResult(torch.empty(B, P, dtype=torch.float64, device=dev),
+                             torch.empty(B, dtype=torch.float64, device=dev),
+                             torch.empty(B, dtype=torch.int32, device=dev),
+                             torch.empty(B, dtype=torch.int32, device=dev),
+                             torch.empty(B, dtype=torch.int32, device=dev))
+    opts = HfFitOpts(max_iter, ls_max, 1 if fixed_iters else 0, free_mask, edm_tol, polish_edm)
+    rc = load().fit_batch(ctx, B, _ptr(c), _dtype_code(c), _ptr(off), _ptr(rg),
+                          ctypes.byref(model.c()), objective, precision, _ptr(th0),
+                          ctypes.byref(opts), _ptr(out.theta), _ptr(out.nll), _ptr(out.status),
+                          _ptr(out.iters), _ptr(out.nevals), _stream(dev))
+    _check(rc, ctx)
+    return out

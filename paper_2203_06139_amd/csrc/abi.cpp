@@ -1,0 +1,348 @@
+// abi.cpp -- the extern "C" boundary of libhistfit.so (declared in
+// include/histfit.h): context and scratch ownership, host-side argument
+// validation, launch-shape selection and kernel dispatch.  Every step of the
+// computation runs in the HIP kernels; this file only checks and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+
+#include "../../include/histfit.h"
+#include "fit_kernels.hpp"
+#include "nll_kernels.hpp"
+
+#define HF_EXPORT extern "C" __attribute__((visibility("default")))
+
+static_assert(HF_NEYMAN == hf::OBJ_NEYMAN && HF_PEARSON == hf::OBJ_PEARSON &&
+                  HF_POISSON == hf::OBJ_POISSON,
+              "objective codes");
+static_assert(HF_U32 == hf::DT_U32 && HF_F32 == hf::DT_F32 && HF_F64 == hf::DT_F64, "dtype codes");
+static_assert(HF_ST_DOMAIN == hf::ST_DOMAIN && HF_ST_NONFINITE == hf::ST_NONFINITE, "status bits");
+
+namespace {
+
+// Largest reduction width: P + 1 with P <= 16.
+constexpr int kMaxNV = 17;
+// Upper bound on the objective kernels' grid; the partial-sum scratch is
+// sized for it once, at context creation, so no call allocates afterwards.
+constexpr int kMaxGrid = 8192;
+
+}  // namespace
+
+struct hf_ctx {
+  int device = 0;
+  int num_cu = 0;
+  int blocks_per_cu = 4;
+  std::string err;
+  double* part = nullptr;
+  int32_t* part_flags = nullptr;
+  unsigned* ticket = nullptr;
+  hf::FitScratch fit;
+};
+
+namespace {
+
+int fail(hf_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(hf_ctx* c, hipError_t e, const char* what) {
+  return fail(c, HF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int use_device(hf_ctx* c) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+  if (cur != c->device) {
+    e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  }
+  return HF_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int check_model(hf_ctx* c, const hf_model* m) {
+  if (!m) return fail(c, HF_EINVAL, "model is NULL");
+  if (m->reserved != 0) return fail(c, HF_EINVAL, "model.reserved must be 0");
+  switch (m->kind) {
+    case HF_GAUSS_POLY:
+      if (m->n_gauss < 0 || m->n_gauss > 4)
+        return fail(c, HF_EUNSUPPORTED, "n_gauss %d outside 0..4", m->n_gauss);
+      if (m->poly_degree < -1 || m->poly_degree > 3)
+        return fail(c, HF_EUNSUPPORTED, "poly_degree %d outside -1..3", m->poly_degree);
+      if (m->n_gauss == 0 && m->poly_degree < 0)
+        return fail(c, HF_EINVAL, "model has no terms");
+      break;
+    case HF_GAUSS_EXP:
+      if (m->n_gauss < 0 || m->n_gauss > 4)
+        return fail(c, HF_EUNSUPPORTED, "n_gauss %d outside 0..4", m->n_gauss);
+      break;
+    case HF_GAUSS2D:
+      return HF_OK;
+    default:
+      return fail(c, HF_EUNSUPPORTED, "unknown model kind %d", m->kind);
+  }
+  if (!std::isfinite(m->t_shift) || !std::isfinite(m->t_scale) || m->t_scale == 0.0)
+    return fail(c, HF_EINVAL, "t_shift/t_scale must be finite and t_scale nonzero");
+  return HF_OK;
+}
+
+int nparams(const hf_model* m) {
+  switch (m->kind) {
+    case HF_GAUSS_POLY:
+      return 3 * m->n_gauss + m->poly_degree + 1;
+    case HF_GAUSS_EXP:
+      return 3 * m->n_gauss + 2;
+    default:
+      return 7;
+  }
+}
+
+int bkg_code(const hf_model* m) {
+  return m->kind == HF_GAUSS_EXP ? hf::BKG_EXP : m->poly_degree;
+}
+
+hf::LaunchFn pick_1d(int ng, int bkg, bool grad, bool f32) {
+  switch (ng) {
+    case 0:
+      return hf::pick_1d_ng0(bkg, grad, f32);
+    case 1:
+      return hf::pick_1d_ng1(bkg, grad, f32);
+    case 2:
+      return hf::pick_1d_ng2(bkg, grad, f32);
+    case 3:
+      return hf::pick_1d_ng3(bkg, grad, f32);
+    case 4:
+      return hf::pick_1d_ng4(bkg, grad, f32);
+    default:
+      return nullptr;
+  }
+}
+
+// Grid for a grid-stride pass over nb bins in 4-bin chunks: at most
+// blocks_per_cu resident blocks per CU, and the chunks split as evenly as
+// that allows (every thread gets ceil or floor of the same count).
+int objective_grid(const hf_ctx* c, int64_t nb) {
+  const int64_t chunks = (nb + 3) / 4;
+  const int64_t per_block = hf::kBlock;
+  int64_t gmax = static_cast<int64_t>(c->num_cu) * c->blocks_per_cu;
+  if (gmax > kMaxGrid) gmax = kMaxGrid;
+  if (gmax < 1) gmax = 1;
+  int64_t need = (chunks + per_block - 1) / per_block;
+  if (need <= gmax) return static_cast<int>(need < 1 ? 1 : need);
+  const int64_t q = (chunks + gmax * per_block - 1) / (gmax * per_block);
+  int64_t g = (chunks + per_block * q - 1) / (per_block * q);
+  return static_cast<int>(g < 1 ? 1 : g);
+}
+
+int check_hist(hf_ctx* c, const hf_hist* h, bool two_d) {
+  if (!h) return fail(c, HF_EINVAL, "hist is NULL");
+  if (!h->counts) return fail(c, HF_EINVAL, "hist.counts is NULL");
+  if (h->reserved != 0) return fail(c, HF_EINVAL, "hist.reserved must be 0");
+  if (h->counts_dtype < HF_U32 || h->counts_dtype > HF_F64)
+    return fail(c, HF_EINVAL, "counts_dtype %d unknown", h->counts_dtype);
+  if (h->nx < 1 || h->ny < 1) return fail(c, HF_EINVAL, "nx, ny must be >= 1");
+  if (!two_d && h->ny != 1) return fail(c, HF_EINVAL, "1D model needs ny == 1");
+  if (h->nx > (int64_t(1) << 40) || h->ny > (int64_t(1) << 40) ||
+      h->nx * h->ny > (int64_t(1) << 50))
+    return fail(c, HF_EINVAL, "histogram too large");
+  if (!(std::isfinite(h->xlo) && std::isfinite(h->xhi) && h->xhi > h->xlo))
+    return fail(c, HF_EINVAL, "x range must be finite with xhi > xlo");
+  if (two_d && !(std::isfinite(h->ylo) && std::isfinite(h->yhi) && h->yhi > h->ylo))
+    return fail(c, HF_EINVAL, "y range must be finite with yhi > ylo");
+  if (!aligned16(h->counts)) return fail(c, HF_EINVAL, "hist.counts must be 16-byte aligned");
+  if (h->weights && !aligned16(h->weights))
+    return fail(c, HF_EINVAL, "hist.weights must be 16-byte aligned");
+  return HF_OK;
+}
+
+int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, int32_t prec,
+                  const double* theta, const double* seed, double* nll_out, double* grad_out,
+                  float* grad_w_out, uint32_t free_mask, int32_t* status_out, hipStream_t stream,
+                  bool grad) {
+  if (!c) return HF_EINVAL;
+  int rc = check_model(c, m);
+  if (rc) return rc;
+  const bool two_d = m->kind == HF_GAUSS2D;
+  rc = check_hist(c, h, two_d);
+  if (rc) return rc;
+  if (obj < HF_NEYMAN || obj > HF_POISSON) return fail(c, HF_EINVAL, "objective %d unknown", obj);
+  if (prec != HF_FP64 && prec != HF_FP32_BIN)
+    return fail(c, HF_EINVAL, "precision %d unknown", prec);
+  if (!theta) return fail(c, HF_EINVAL, "theta is NULL");
+  if (!nll_out) return fail(c, HF_EINVAL, "nll_out is NULL");
+  if (grad && !grad_out) return fail(c, HF_EINVAL, "grad_out is NULL");
+  if (grad_w_out && !aligned16(grad_w_out))
+    return fail(c, HF_EINVAL, "grad_w_out must be 16-byte aligned");
+  rc = use_device(c);
+  if (rc) return rc;
+
+  hf::LaunchFn fn = two_d ? hf::pick_2d(grad, prec == HF_FP32_BIN)
+                          : pick_1d(m->n_gauss, bkg_code(m), grad, prec == HF_FP32_BIN);
+  if (!fn) return fail(c, HF_EUNSUPPORTED, "no kernel for this model");
+
+  hf::NllArgs a{};
+  a.counts = h->counts;
+  a.weights = h->weights;
+  a.nx = h->nx;
+  a.ny = two_d ? h->ny : 1;
+  a.dtype = h->counts_dtype;
+  a.obj = obj;
+  a.hx = (h->xhi - h->xlo) / static_cast<double>(h->nx);
+  a.x0 = h->xlo + 0.5 * a.hx;
+  if (two_d) {
+    a.hy = (h->yhi - h->ylo) / static_cast<double>(h->ny);
+    a.y0 = h->ylo + 0.5 * a.hy;
+  }
+  a.theta = theta;
+  a.seed = seed;
+  a.nll_out = nll_out;
+  a.grad_out = grad_out;
+  a.grad_w_out = grad_w_out;
+  a.status_out = status_out;
+  a.free_mask = free_mask;
+  a.P = nparams(m);
+  a.t_shift = m->t_shift;
+  a.t_scale = m->t_scale;
+  a.part = c->part;
+  a.part_flags = c->part_flags;
+  a.ticket = c->ticket;
+  const int grid = objective_grid(c, a.nx * a.ny);
+  hipError_t e = fn(a, grid, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return HF_OK;
+}
+
+}  // namespace
+
+HF_EXPORT int hf_ctx_create(hf_ctx** out, int device) {
+  if (!out) return HF_EINVAL;
+  *out = nullptr;
+  hf_ctx* c = new hf_ctx();
+  c->device = device;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    delete c;
+    return HF_EHIP;
+  }
+  e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess || c->num_cu < 1) {
+    delete c;
+    return HF_EHIP;
+  }
+  if (const char* s = std::getenv("HF_BLOCKS_PER_CU")) {
+    const int v = std::atoi(s);
+    if (v >= 1 && v <= 32) c->blocks_per_cu = v;
+  }
+  const size_t part_bytes = sizeof(double) * kMaxNV * kMaxGrid;
+  if (hipMalloc(&c->part, part_bytes) != hipSuccess ||
+      hipMalloc(&c->part_flags, sizeof(int32_t) * kMaxGrid) != hipSuccess ||
+      hipMalloc(&c->ticket, 256) != hipSuccess || hipMemset(c->ticket, 0, 256) != hipSuccess ||
+      hf::fit_scratch_init(&c->fit) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    hf_ctx_destroy(c);
+    return HF_ENOMEM;
+  }
+  *out = c;
+  return HF_OK;
+}
+
+HF_EXPORT void hf_ctx_destroy(hf_ctx* c) {
+  if (!c) return;
+  int cur = -1;
+  if (hipGetDevice(&cur) == hipSuccess && cur != c->device) (void)hipSetDevice(c->device);
+  if (c->part) (void)hipFree(c->part);
+  if (c->part_flags) (void)hipFree(c->part_flags);
+  if (c->ticket) (void)hipFree(c->ticket);
+  hf::fit_scratch_free(&c->fit);
+  if (cur >= 0 && cur != c->device) (void)hipSetDevice(cur);
+  delete c;
+}
+
+HF_EXPORT const char* hf_last_error(const hf_ctx* c) { return c ? c->err.c_str() : ""; }
+
+HF_EXPORT int hf_model_nparams(const hf_model* m) {
+  const int rc = check_model(nullptr, m);
+  if (rc) return rc;
+  return nparams(m);
+}
+
+HF_EXPORT int nll_eval(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, int32_t prec,
+                       const double* theta, double* nll_out, int32_t* status_out,
+                       hf_stream_t stream) {
+  return run_objective(c, h, m, obj, prec, theta, nullptr, nll_out, nullptr, nullptr, 0u,
+                       status_out, reinterpret_cast<hipStream_t>(stream), false);
+}
+
+HF_EXPORT int nll_grad(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, int32_t prec,
+                       const double* theta, const double* seed, double* nll_out, double* grad_out,
+                       float* grad_w_out, uint32_t free_mask, int32_t* status_out,
+                       hf_stream_t stream) {
+  return run_objective(c, h, m, obj, prec, theta, seed, nll_out, grad_out, grad_w_out, free_mask,
+                       status_out, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
+                        const int64_t* offsets, const double* ranges, const hf_model* m,
+                        int32_t obj, int32_t prec, const double* theta0, const hf_fit_opts* o,
+                        double* theta_out, double* nll_out, int32_t* status, int32_t* iters,
+                        int32_t* nevals, hf_stream_t stream) {
+  if (!c) return HF_EINVAL;
+  int rc = check_model(c, m);
+  if (rc) return rc;
+  if (m->kind == HF_GAUSS2D) return fail(c, HF_EUNSUPPORTED, "fit_batch takes 1D models only");
+  if (B < 0) return fail(c, HF_EINVAL, "B must be >= 0");
+  if (B == 0) return HF_OK;
+  if (!counts || !offsets || !ranges || !theta0 || !o || !theta_out || !nll_out || !status ||
+      !iters || !nevals)
+    return fail(c, HF_EINVAL, "a fit_batch pointer argument is NULL");
+  if (dtype < HF_U32 || dtype > HF_F64) return fail(c, HF_EINVAL, "counts_dtype %d unknown", dtype);
+  if (obj < HF_NEYMAN || obj > HF_POISSON) return fail(c, HF_EINVAL, "objective %d unknown", obj);
+  if (prec != HF_FP64 && prec != HF_FP32_BIN)
+    return fail(c, HF_EINVAL, "precision %d unknown", prec);
+  if (o->max_iter < 1 || o->ls_max < 1 || o->ls_max > 60 || !(o->edm_tol >= 0.0))
+    return fail(c, HF_EINVAL, "fit options out of range");
+  rc = use_device(c);
+  if (rc) return rc;
+
+  hf::FitArgs a{};
+  a.B = B;
+  a.counts = counts;
+  a.dtype = dtype;
+  a.offsets = offsets;
+  a.ranges = ranges;
+  a.obj = obj;
+  a.f32 = prec == HF_FP32_BIN ? 1 : 0;
+  a.theta0 = theta0;
+  a.theta_out = theta_out;
+  a.nll_out = nll_out;
+  a.status = status;
+  a.iters = iters;
+  a.nevals = nevals;
+  a.max_iter = o->max_iter;
+  a.ls_max = o->ls_max;
+  a.fixed_iters = o->fixed_iters;
+  a.free_mask = o->free_mask;
+  a.edm_tol = o->edm_tol;
+  a.polish_edm = o->polish_edm;
+  a.t_shift = m->t_shift;
+  a.t_scale = m->t_scale;
+  a.P = nparams(m);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hf::launch_fit(m->n_gauss, bkg_code(m), a, c->num_cu, &c->fit, s);
+  if (e == hipErrorNotSupported) return fail(c, HF_EUNSUPPORTED, "no fit kernel for this model");
+  if (e != hipSuccess) return hip_fail(c, e, "fit launch");
+  return HF_OK;
+}

@@ -1,0 +1,104 @@
+// fit.hip -- fitter scratch, the longest-first ordering kernel and the launch
+// of the persistent fit kernel.
+#include "fit_impl.hpp"
+
+namespace hf {
+
+namespace {
+
+// Rank every histogram by size, longest first, ties by index: a strict total
+// order, so the ranks form a permutation.  O(B^2) comparisons staged through
+// LDS tiles; used for B <= kMaxRankB.
+constexpr int kMaxRankB = 1 << 16;
+
+__global__ __launch_bounds__(kBlock) void k_rank_sizes(const int64_t* __restrict__ offsets, int B,
+                                                      int32_t* __restrict__ order) {
+  __shared__ int64_t tile[kBlock];
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  const int64_t mine = b < B ? offsets[b + 1] - offsets[b] : 0;
+  int rank = 0;
+  for (int j0 = 0; j0 < B; j0 += kBlock) {
+    const int j = j0 + threadIdx.x;
+    tile[threadIdx.x] = j < B ? offsets[j + 1] - offsets[j] : 0;
+    __syncthreads();
+    const int lim = min(kBlock, B - j0);
+    for (int q = 0; q < lim; ++q) {
+      const int64_t o = tile[q];
+      rank += (o > mine) || (o == mine && j0 + q < b);
+    }
+    __syncthreads();
+  }
+  if (b < B) order[rank] = b;
+}
+
+FitLaunchFn pick_fit(int ng, int bkg) {
+  switch (ng) {
+    case 0:
+      return pick_fit_ng0(bkg);
+    case 1:
+      return pick_fit_ng1(bkg);
+    case 2:
+      return pick_fit_ng2(bkg);
+    case 3:
+      return pick_fit_ng3(bkg);
+    case 4:
+      return pick_fit_ng4(bkg);
+    default:
+      return nullptr;
+  }
+}
+
+}  // namespace
+
+hipError_t fit_scratch_init(FitScratch* s) {
+  hipError_t e = hipMalloc(&s->counters, 256);
+  if (e != hipSuccess) return e;
+  if (const char* v = std::getenv("HF_FIT_WG_PER_CU")) {
+    const int k = std::atoi(v);
+    if (k >= 1 && k <= 16) s->wg_per_cu = k;
+  }
+  return hipMemset(s->counters, 0, 256);
+}
+
+void fit_scratch_free(FitScratch* s) {
+  if (s->order) (void)hipFree(s->order);
+  if (s->counters) (void)hipFree(s->counters);
+  s->order = nullptr;
+  s->counters = nullptr;
+  s->cap = 0;
+}
+
+hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s, hipStream_t st) {
+  FitLaunchFn fn = pick_fit(n_gauss, bkg);
+  if (!fn) return hipErrorNotSupported;
+  a.sorted = a.B <= kMaxRankB ? 1 : 0;
+  if (a.sorted && a.B > s->cap) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusNone) return hipErrorStreamCaptureUnsupported;
+    if (s->order) {
+      e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return e;
+      (void)hipFree(s->order);
+      s->order = nullptr;
+      s->cap = 0;
+    }
+    e = hipMalloc(&s->order, sizeof(int32_t) * static_cast<size_t>(a.B));
+    if (e != hipSuccess) return e;
+    s->cap = a.B;
+  }
+  a.order = s->order;
+  a.counters = s->counters;
+  if (a.sorted) {
+    hipLaunchKernelGGL(k_rank_sizes, dim3((a.B + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                       a.offsets, a.B, a.order);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  int grid = num_cu * s->wg_per_cu;
+  if (grid > a.B) grid = a.B;
+  return fn(a, grid, st);
+}
+
+}  // namespace hf

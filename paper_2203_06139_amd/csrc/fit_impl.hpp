@@ -1,0 +1,350 @@
+// fit_impl.hpp -- persistent batched BFGS fitter (templates).
+//
+// Algorithm per histogram (the optimiser step of a gradient-based fit, paper
+// sec. 4; BFGS and the first-step scaling follow Nocedal & Wright,
+// "Numerical Optimization", ch. 6 and eq. 6.20):
+//   scaled coordinates u_k = (theta_k - theta0_k)/sigma_k for the free
+//   parameters, sigma by parameter kind (amplitude max(|A0|,1), mean
+//   range/100, width |s0|, background max(|c0|,1));  H = I;
+//   repeat: p = -H g;  EDM = g^T H g / 2;  stop when EDM < max(edm_tol,
+//   4 eps |f|);  if g^T p >= 0 restart from H = I;  backtracking Armijo
+//   (c1 = 1e-4, alpha halved up to ls_max times; non-finite f rejected);
+//   s = alpha p, y = g_new - g;  if s^T y > 1e-12 |s||y| the BFGS inverse
+//   update (scaled by s^T y / y^T y before the first one).
+// Finally |s| for every width, Gaussians ordered by mean, and the NLL
+// re-evaluated with FP64 bins.
+//
+// Work split: the whole workgroup evaluates the objective and gradient over
+// the histogram's bins (bin_1d + block_sum); the O(P^2) BFGS algebra is
+// spread over the first P or P^2 threads; scalar decisions are computed
+// redundantly by every thread from the same LDS values, so control flow
+// stays uniform without extra barriers.
+#pragma once
+
+#include <float.h>
+#include <stdlib.h>
+
+#include "device.hpp"
+#include "fit_kernels.hpp"
+
+namespace hf {
+
+enum : int { FIT_CONVERGED = 0, FIT_MAXITER = 1, FIT_LSFAIL = 2, FIT_NONFINITE = 3,
+             FIT_DOMAIN = 4, FIT_BADHIST = 5 };
+
+__device__ __forceinline__ double count_at(const void* base, int dtype, int64_t i) {
+  if (dtype == DT_U32) return static_cast<const uint32_t*>(base)[i];
+  if (dtype == DT_F32) return static_cast<const float*>(base)[i];
+  return static_cast<const double*>(base)[i];
+}
+
+template <int NG, int BKG>
+struct FitShared {
+  static constexpr int P = Shape1D<NG, BKG>::P;
+  static constexpr int NV = P + 1;
+  double th[P], th0[P], sig[P];
+  double u[P], g[P], un[P], gn[P], pv[P], tmp[P], sv[P], yv[P], Hy[P];
+  double H[P * P];  // row stride P; the leading nf x nf block is used
+  double tot[NV];
+  double red[kWaves][NV];
+  int redf[kWaves];
+  int totf;
+  int fidx[P];
+  int nf;
+  int h;
+};
+
+// Objective and scaled-coordinate gradient of one histogram at sm.th,
+// evaluated by the whole workgroup.  Leaves f in sm.tot[0] and
+// dL/dtheta_k in sm.tot[1 + k].
+template <int NG, int BKG, bool F32BIN>
+__device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG>& sm, int64_t off, int64_t nb,
+                        double x0, double hx) {
+  constexpr int NV = FitShared<NG, BKG>::NV;
+  Model1D<NG, BKG> M;
+  M.init(sm.th, a.t_shift, a.t_scale);
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  int flags = 0;
+  const int obj = a.obj;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * kBlock < nb; i += 4 * kBlock) {
+    double n[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) n[k] = count_at(a.counts, a.dtype, off + i + k * kBlock);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      bin_1d<NG, BKG, true, F32BIN>(M, obj, fma(static_cast<double>(i + k * kBlock), hx, x0), n[k],
+                                    1.0, acc, flags);
+  }
+  for (; i < nb; i += kBlock)
+    bin_1d<NG, BKG, true, F32BIN>(M, obj, fma(static_cast<double>(i), hx, x0),
+                                  count_at(a.counts, a.dtype, off + i), 1.0, acc, flags);
+  block_sum<NV>(acc, flags, sm.tot, &sm.totf, sm.red, sm.redf);
+  if (threadIdx.x >= 1 && threadIdx.x < NV) sm.tot[threadIdx.x] *= M.final_factor(threadIdx.x);
+  __syncthreads();
+}
+
+// f(u) and g_u = sigma * dL/dtheta at theta = theta0 + sigma * u.
+template <int NG, int BKG>
+__device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG>& sm, const double* uu,
+                               double* gout, bool f32, int64_t off, int64_t nb, double x0,
+                               double hx) {
+  constexpr int P = FitShared<NG, BKG>::P;
+  const int tid = threadIdx.x;
+  if (tid < P) sm.th[tid] = sm.th0[tid];
+  __syncthreads();
+  if (tid < sm.nf) {
+    const int k = sm.fidx[tid];
+    sm.th[k] = fma(sm.sig[k], uu[tid], sm.th0[k]);
+  }
+  __syncthreads();
+  if (f32)
+    wg_eval<NG, BKG, true>(a, sm, off, nb, x0, hx);
+  else
+    wg_eval<NG, BKG, false>(a, sm, off, nb, x0, hx);
+  if (tid < sm.nf) {
+    const int k = sm.fidx[tid];
+    gout[tid] = sm.sig[k] * sm.tot[1 + k];
+  }
+  const double f = sm.tot[0];
+  __syncthreads();
+  return f;
+}
+
+template <int NG, int BKG>
+__device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, int b) {
+  constexpr int P = FitShared<NG, BKG>::P;
+  constexpr int NB = Shape1D<NG, BKG>::NB;
+  const int tid = threadIdx.x;
+  const int64_t off = a.offsets[b];
+  const int64_t nb = a.offsets[b + 1] - off;
+  const double lo = a.ranges[2 * b], hi = a.ranges[2 * b + 1];
+  if (!(nb >= 1) || !(hi > lo) || !__builtin_isfinite(lo) || !__builtin_isfinite(hi)) {
+    if (tid < P) a.theta_out[static_cast<int64_t>(b) * P + tid] = a.theta0[static_cast<int64_t>(b) * P + tid];
+    if (tid == 0) {
+      a.nll_out[b] = __builtin_nan("");
+      a.status[b] = FIT_BADHIST;
+      a.iters[b] = 0;
+      a.nevals[b] = 0;
+    }
+    __syncthreads();
+    return;
+  }
+  const double hx = (hi - lo) / static_cast<double>(nb);
+  const double x0 = lo + 0.5 * hx;
+
+  if (tid < P) sm.th0[tid] = a.theta0[static_cast<int64_t>(b) * P + tid];
+  __syncthreads();
+  if (tid == 0) {
+    const double rx = hi - lo;
+    int k = 0;
+    for (int g = 0; g < NG; ++g, k += 3) {
+      sm.sig[k] = fmax(fabs(sm.th0[k]), 1.0);
+      sm.sig[k + 1] = rx / 100.0;
+      sm.sig[k + 2] = fabs(sm.th0[k + 2]) > 0.0 ? fabs(sm.th0[k + 2]) : rx / 100.0;
+    }
+    for (int j = 0; j < NB; ++j) sm.sig[k + j] = fmax(fabs(sm.th0[k + j]), 1.0);
+    int nf = 0;
+    for (int q = 0; q < P; ++q)
+      if (a.free_mask == 0u || ((a.free_mask >> q) & 1u)) sm.fidx[nf++] = q;
+    sm.nf = nf;
+  }
+  if (tid < P) sm.u[tid] = 0.0;
+  for (int t = tid; t < P * P; t += kBlock) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
+  __syncthreads();
+  const int nf = sm.nf;
+
+  bool f32 = a.f32 != 0;
+  double f = wg_objective<NG, BKG>(a, sm, sm.u, sm.g, f32, off, nb, x0, hx);
+  int nev = 1, it = 0, status = FIT_MAXITER;
+  bool first = true;
+  if (!__builtin_isfinite(f)) {
+    status = (f == __builtin_inf()) ? FIT_DOMAIN : FIT_NONFINITE;
+  } else {
+    while (it < a.max_iter) {
+      if (tid < nf) {
+        double hg = 0.0;
+        for (int c = 0; c < nf; ++c) hg += sm.H[tid * P + c] * sm.g[c];
+        sm.pv[tid] = -hg;
+        sm.tmp[tid] = sm.g[tid] * hg;
+      }
+      __syncthreads();
+      double edm = 0.0;
+      for (int q = 0; q < nf; ++q) edm += sm.tmp[q];
+      edm *= 0.5;
+      const double goal = fmax(a.edm_tol, 4.0 * DBL_EPSILON * fabs(f));
+      if (f32 && a.polish_edm > 0.0 && edm < a.polish_edm) {
+        // switch to FP64 bins for the rest of the fit
+        f32 = false;
+        f = wg_objective<NG, BKG>(a, sm, sm.u, sm.g, false, off, nb, x0, hx);
+        ++nev;
+        if (!__builtin_isfinite(f)) {
+          status = (f == __builtin_inf()) ? FIT_DOMAIN : FIT_NONFINITE;
+          break;
+        }
+        continue;
+      }
+      if (!a.fixed_iters && edm < goal) {
+        status = FIT_CONVERGED;
+        break;
+      }
+      double slope = 0.0;
+      for (int q = 0; q < nf; ++q) slope += sm.g[q] * sm.pv[q];
+      if (!(slope < 0.0)) {  // H lost positive definiteness: restart from I
+        __syncthreads();
+        for (int t = tid; t < P * P; t += kBlock) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
+        if (tid < nf) sm.pv[tid] = -sm.g[tid];
+        first = true;
+        __syncthreads();
+        slope = 0.0;
+        for (int q = 0; q < nf; ++q) slope -= sm.g[q] * sm.g[q];
+      }
+      double alpha = 1.0, fn = 0.0;
+      bool accepted = false;
+      for (int ls = 0; ls < a.ls_max; ++ls) {
+        if (tid < nf) sm.un[tid] = sm.u[tid] + alpha * sm.pv[tid];
+        __syncthreads();
+        fn = wg_objective<NG, BKG>(a, sm, sm.un, sm.gn, f32, off, nb, x0, hx);
+        ++nev;
+        if (__builtin_isfinite(fn) && fn <= f + 1e-4 * alpha * slope) {
+          accepted = true;
+          break;
+        }
+        alpha *= 0.5;
+      }
+      if (!accepted) {
+        status = (edm < goal) ? FIT_CONVERGED : FIT_LSFAIL;
+        break;
+      }
+      ++it;
+      if (tid < nf) {
+        sm.sv[tid] = sm.un[tid] - sm.u[tid];
+        sm.yv[tid] = sm.gn[tid] - sm.g[tid];
+      }
+      __syncthreads();
+      double sy = 0.0, yy = 0.0, ss = 0.0;
+      for (int q = 0; q < nf; ++q) {
+        sy += sm.sv[q] * sm.yv[q];
+        yy += sm.yv[q] * sm.yv[q];
+        ss += sm.sv[q] * sm.sv[q];
+      }
+      if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
+        if (first) {
+          const double gam = sy / yy;
+          for (int t = tid; t < nf * nf; t += kBlock) sm.H[(t / nf) * P + t % nf] *= gam;
+          first = false;
+          __syncthreads();
+        }
+        if (tid < nf) {
+          double hy = 0.0;
+          for (int c = 0; c < nf; ++c) hy += sm.H[tid * P + c] * sm.yv[c];
+          sm.Hy[tid] = hy;
+        }
+        __syncthreads();
+        double yHy = 0.0;
+        for (int q = 0; q < nf; ++q) yHy += sm.yv[q] * sm.Hy[q];
+        const double rho = 1.0 / sy;
+        const double cc = rho * rho * yHy + rho;
+        for (int t = tid; t < nf * nf; t += kBlock) {
+          const int r = t / nf, c = t % nf;
+          sm.H[r * P + c] += -rho * (sm.Hy[r] * sm.sv[c] + sm.sv[r] * sm.Hy[c]) + cc * sm.sv[r] * sm.sv[c];
+        }
+      }
+      if (tid < nf) {
+        sm.u[tid] = sm.un[tid];
+        sm.g[tid] = sm.gn[tid];
+      }
+      __syncthreads();
+      f = fn;
+    }
+  }
+  double nll = f;
+  if (f32 && __builtin_isfinite(f)) nll = wg_objective<NG, BKG>(a, sm, sm.u, sm.gn, false, off, nb, x0, hx);
+  // final parameters, canonicalised
+  if (tid < P) sm.th[tid] = sm.th0[tid];
+  __syncthreads();
+  if (tid < nf) {
+    const int k = sm.fidx[tid];
+    sm.th[k] = fma(sm.sig[k], sm.u[tid], sm.th0[k]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int g = 0; g < NG; ++g) sm.th[3 * g + 2] = fabs(sm.th[3 * g + 2]);
+    for (int p = 1; p < NG; ++p)
+      for (int q = p; q > 0 && sm.th[3 * q + 1] < sm.th[3 * (q - 1) + 1]; --q)
+        for (int r = 0; r < 3; ++r) {
+          const double t = sm.th[3 * q + r];
+          sm.th[3 * q + r] = sm.th[3 * (q - 1) + r];
+          sm.th[3 * (q - 1) + r] = t;
+        }
+    a.nll_out[b] = nll;
+    a.status[b] = status;
+    a.iters[b] = it;
+    a.nevals[b] = nev;
+  }
+  __syncthreads();
+  if (tid < P) a.theta_out[static_cast<int64_t>(b) * P + tid] = sm.th[tid];
+  __syncthreads();
+}
+
+template <int NG, int BKG>
+__global__ __launch_bounds__(kBlock) void k_fit(FitArgs a) {
+  __shared__ FitShared<NG, BKG> sm;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) sm.h = static_cast<int>(atomicAdd(&a.counters[0], 1u));
+    __syncthreads();
+    const int h = sm.h;
+    __syncthreads();
+    if (h >= a.B) break;
+    fit_one<NG, BKG>(a, sm, a.sorted ? a.order[h] : h);
+  }
+  // the last workgroup to leave re-arms the queue for the next launch
+  if (tid == 0) {
+    __threadfence();
+    const unsigned d = atomicAdd(&a.counters[1], 1u);
+    if (d == gridDim.x - 1) {
+      atomicExch(&a.counters[0], 0u);
+      atomicExch(&a.counters[1], 0u);
+    }
+  }
+}
+
+template <int NG, int BKG>
+hipError_t launch_fit_kernel(const FitArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_fit<NG, BKG>), dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+using FitLaunchFn = hipError_t (*)(const FitArgs&, int, hipStream_t);
+
+template <int NG>
+FitLaunchFn pick_fit_ng(int bkg) {
+  switch (bkg) {
+    case BKG_NONE:
+      if constexpr (NG == 0) return nullptr;
+      else return &launch_fit_kernel<NG, BKG_NONE>;
+    case 0:
+      return &launch_fit_kernel<NG, 0>;
+    case 1:
+      return &launch_fit_kernel<NG, 1>;
+    case 2:
+      return &launch_fit_kernel<NG, 2>;
+    case 3:
+      return &launch_fit_kernel<NG, 3>;
+    case BKG_EXP:
+      return &launch_fit_kernel<NG, BKG_EXP>;
+    default:
+      return nullptr;
+  }
+}
+
+FitLaunchFn pick_fit_ng0(int bkg);
+FitLaunchFn pick_fit_ng1(int bkg);
+FitLaunchFn pick_fit_ng2(int bkg);
+FitLaunchFn pick_fit_ng3(int bkg);
+FitLaunchFn pick_fit_ng4(int bkg);
+
+}  // namespace hf

@@ -1,0 +1,6 @@
+// fit_ng0.hip -- batched fitter kernels for models with 0 Gaussian(s).
+#include "fit_impl.hpp"
+
+namespace hf {
+FitLaunchFn pick_fit_ng0(int bkg) { return pick_fit_ng<0>(bkg); }
+}  // namespace hf

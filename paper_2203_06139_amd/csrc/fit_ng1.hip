@@ -1,0 +1,6 @@
+// fit_ng1.hip -- batched fitter kernels for models with 1 Gaussian(s).
+#include "fit_impl.hpp"
+
+namespace hf {
+FitLaunchFn pick_fit_ng1(int bkg) { return pick_fit_ng<1>(bkg); }
+}  // namespace hf

@@ -1,0 +1,6 @@
+// fit_ng2.hip -- batched fitter kernels for models with 2 Gaussian(s).
+#include "fit_impl.hpp"
+
+namespace hf {
+FitLaunchFn pick_fit_ng2(int bkg) { return pick_fit_ng<2>(bkg); }
+}  // namespace hf

@@ -1,0 +1,6 @@
+// fit_ng4.hip -- batched fitter kernels for models with 4 Gaussian(s).
+#include "fit_impl.hpp"
+
+namespace hf {
+FitLaunchFn pick_fit_ng4(int bkg) { return pick_fit_ng<4>(bkg); }
+}  // namespace hf

@@ -1,0 +1,7 @@
+// nll1d_ng1.hip -- 1D objective kernels with 1 Gaussian(s); one translation
+// unit per Gaussian count so the instantiations compile in parallel.
+#include "nll_kernels.hpp"
+
+namespace hf {
+LaunchFn pick_1d_ng1(int bkg, bool grad, bool f32) { return pick_1d_ng<1>(bkg, grad, f32); }
+}  // namespace hf

@@ -1,0 +1,7 @@
+// nll1d_ng4.hip -- 1D objective kernels with 4 Gaussian(s); one translation
+// unit per Gaussian count so the instantiations compile in parallel.
+#include "nll_kernels.hpp"
+
+namespace hf {
+LaunchFn pick_1d_ng4(int bkg, bool grad, bool f32) { return pick_1d_ng<4>(bkg, grad, f32); }
+}  // namespace hf

@@ -1,0 +1,123 @@
+"""GPU fits (fit_batch) against the oracle's BFGS on the same starts.
+
+Agreement criterion: both fits converge and |NLL_gpu - NLL_oracle| < 1e-6
+(absolute, saturated Poisson scale, FP64 re-evaluation); the fitted
+parameters then agree to within a small fraction of their scale.
+"""
+import numpy as np
+import pytest
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def orc_model(orc, spec):
+    return orc.Model(spec["kind"], spec["n_gauss"], spec["poly_degree"], spec["t_shift"],
+                     spec["t_scale"])
+
+
+def to_dev_counts(counts):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(counts).view(np.int32)).cuda()
+
+
+def run_fit(hf, spec, counts, offsets, ranges, theta0, **kw):
+    import torch
+    r = hf.fit_batch(to_dev_counts(counts), torch.as_tensor(offsets), torch.as_tensor(ranges),
+                     hf.Model.from_spec(spec), torch.as_tensor(theta0), **kw)
+    torch.cuda.synchronize()
+    return (r.theta.cpu().numpy(), r.nll.cpu().numpy(), r.status.cpu().numpy(),
+            r.iters.cpu().numpy(), r.nevals.cpu().numpy())
+
+
+@pytest.mark.parametrize("obj", [2, 0])
+def test_single_fit_10k_bins(hf, orc, obj):
+    c = datagen.single_fit_case()
+    th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], [0, c["counts"].size],
+                                  [c["range"]], c["theta0"][None, :], objective=obj)
+    ref = orc.fit(orc_model(orc, c["spec"]), obj, c["counts"], c["theta0"], c["range"])
+    assert ref.status == 0 and st[0] == 0, (ref, st)
+    assert abs(nll[0] - ref.nll) < 1e-6, (nll[0], ref.nll)
+    np.testing.assert_allclose(th[0], ref.theta, rtol=1e-5, atol=1e-6)
+    assert it[0] > 3 and ne[0] >= it[0]
+
+
+def _subset(B, seed=3):
+    c = datagen.batch_case(seed=seed, B=B, lo_bins=256, hi_bins=16384)
+    rng = np.random.default_rng(seed + 77)
+    th0 = c["theta_true"].copy()
+    th0[:, 0] *= 1 + 0.05 * rng.standard_normal(B)
+    th0[:, 1] += 0.3 * th0[:, 2] * rng.standard_normal(B)
+    th0[:, 2] *= 1 + 0.05 * rng.standard_normal(B)
+    th0[:, 3] += 0.05 * rng.standard_normal(B)
+    th0[:, 4] += 0.05 * rng.standard_normal(B)
+    return c, th0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_fits_match_oracle(hf, orc, prec):
+    c, th0 = _subset(96)
+    kw = dict(objective=2, precision=prec, polish_edm=1e-3 if prec else 0.0)
+    th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], th0, **kw)
+    rth, rnll, rst, rit, rne = orc.fit_many(orc_model(orc, c["spec"]), 2, c["counts"],
+                                           c["offsets"], c["ranges"], th0, nthreads=8)
+    both = (st == 0) & (rst == 0)
+    assert both.mean() > 0.9, (st, rst)
+    dn = np.abs(nll - rnll)[both]
+    assert np.all(dn < 1e-6), dn.max()
+    scale = np.maximum(np.abs(rth[both]), 1e-3)
+    assert np.all(np.abs(th[both] - rth[both]) <= 1e-3 * scale)
+
+
+def test_bad_histograms_and_status_codes(hf):
+    c, th0 = _subset(4)
+    off = c["offsets"].copy()
+    off[2] = off[1]  # histogram 1 empty
+    ranges = c["ranges"].copy()
+    ranges[3] = (1.0, 1.0)  # histogram 3: empty range
+    th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], off, ranges, th0)
+    assert st[1] == hf.FIT_BADHIST and st[3] == hf.FIT_BADHIST
+    np.testing.assert_array_equal(th[1], th0[1])
+    assert st[0] == hf.FIT_CONVERGED
+    th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], th0,
+                                  max_iter=1)
+    assert np.all(st == hf.FIT_MAXITER) and np.all(it == 1)
+
+
+def test_fit_batch_repeatable_and_graph_replay(hf):
+    import torch
+    c, th0 = _subset(64, seed=11)
+    counts = to_dev_counts(c["counts"])
+    off = torch.as_tensor(c["offsets"]).cuda()
+    rg = torch.as_tensor(c["ranges"]).cuda()
+    t0 = torch.as_tensor(th0).cuda()
+    m = hf.Model.from_spec(c["spec"])
+    eager = hf.fit_batch(counts, off, rg, m, t0, precision=1, polish_edm=1e-3)
+    torch.cuda.synchronize()
+    ref = (eager.theta.clone(), eager.nll.clone(), eager.status.clone())
+    again = hf.fit_batch(counts, off, rg, m, t0, precision=1, polish_edm=1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(again.theta, ref[0]) and torch.equal(again.nll, ref[1])
+    # capture into a graph and replay, with eager work between replays
+    out = hf.FitBatchResult(torch.empty_like(ref[0]), torch.empty_like(ref[1]),
+                            torch.empty_like(ref[2]), torch.empty_like(ref[2]),
+                            torch.empty_like(ref[2]))
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        hf.fit_batch(counts, off, rg, m, t0, precision=1, polish_edm=1e-3, out=out)  # warm-up
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            hf.fit_batch(counts, off, rg, m, t0, precision=1, polish_edm=1e-3, out=out)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        out.theta.zero_()
+        out.nll.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out.theta, ref[0]) and torch.equal(out.nll, ref[1])
+        x = torch.randn(1000, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        del x
