@@ -28,9 +28,11 @@
  *           to a device status word (bit field, hf_bin_status) so that no
  *           call forces a host synchronisation:
  *             HF_ST_DOMAIN     a bin had mu <= 0 where the objective needs
- *                              mu > 0; the NLL is +inf and that bin adds
- *                              nothing to the gradient;
- *             HF_ST_NONFINITE  theta held a NaN or infinity.
+ *                              mu > 0; the NLL is +inf and, the objective
+ *                              not being differentiable there, the gradient
+ *                              is NaN;
+ *             HF_ST_NONFINITE  theta held a NaN or infinity; the NLL and
+ *                              gradient outputs are then NaN.
  * Threads.  A context is not thread safe and its calls must not overlap:
  *           use one context per host thread or per concurrently used stream.
  *           Calls serialised on one stream may share a context.
@@ -150,7 +152,7 @@ int nll_eval(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t ob
  *              seed * dL/dtheta; entries whose bit is clear in free_mask are
  *              set to 0.  free_mask = 0 selects every parameter.
  *   grad_w_out device f32[nx*ny] or NULL, 16-byte aligned: seed * dL/dw_i =
- *              seed * l_i per bin (+inf for domain-error bins).
+ *              seed * l_i per bin (unspecified for domain-error bins).
  *   status_out as for nll_eval.                                           */
 int nll_grad(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t objective,
              int32_t precision, const double* theta, const double* seed, double* nll_out,

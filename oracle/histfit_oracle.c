@@ -41,8 +41,9 @@
  *   2 Poisson, saturated form without the factor 2:
  *           l = mu - n + n ln(n/mu) for n > 0, l = mu for n = 0;
  *           mu <= 0 with n > 0, or mu < 0 with n = 0, is a domain error.
- * A domain error makes that bin's l = +inf, contributes nothing to the
- * gradient, and sets status bit 0.  A non-finite theta sets status bit 1.
+ * A domain error makes that bin's l = +inf and sets status bit 0; the
+ * objective is then +inf and not differentiable, so the gradient is NaN.
+ * A non-finite theta sets status bit 1.
  *
  * The fitter (or_fit) is a textbook BFGS on the inverse Hessian with a
  * backtracking Armijo line search, stopping on the estimated distance to
@@ -388,7 +389,7 @@ int or_nll_grad_mt(const or_model* m, int obj, const double* counts, const doubl
   if (!theta_finite(theta, P)) status |= OR_ST_NONFINITE;
   *nll_out = nsum_value(&nll);
   if (grad_out)
-    for (int k = 0; k < P; ++k) grad_out[k] = nsum_value(&grad[k]);
+    for (int k = 0; k < P; ++k) grad_out[k] = (status & OR_ST_DOMAIN) ? NAN : nsum_value(&grad[k]);
   if (scale_out) {
     scale_out[0] = nsum_value(&nll_abs);
     for (int k = 0; k < P; ++k) scale_out[1 + k] = nsum_value(&grad_abs[k]);

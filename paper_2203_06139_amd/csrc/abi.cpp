@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <map>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -35,11 +36,13 @@ constexpr int kMaxGrid = 8192;
 struct hf_ctx {
   int device = 0;
   int num_cu = 0;
-  int blocks_per_cu = 4;
+  int blocks_per_cu = 0;  // 0: as many as the kernel's occupancy allows
+  std::map<hf::LaunchFn, int> occupancy;
   std::string err;
   double* part = nullptr;
   int32_t* part_flags = nullptr;
   unsigned* ticket = nullptr;
+  double2* log_lut = nullptr;
   hf::FitScratch fit;
 };
 
@@ -115,30 +118,31 @@ int bkg_code(const hf_model* m) {
   return m->kind == HF_GAUSS_EXP ? hf::BKG_EXP : m->poly_degree;
 }
 
-hf::LaunchFn pick_1d(int ng, int bkg, bool grad, bool f32) {
+hf::LaunchFn pick_1d(int ng, int bkg, int obj, bool grad, bool f32) {
   switch (ng) {
     case 0:
-      return hf::pick_1d_ng0(bkg, grad, f32);
+      return hf::pick_1d_ng0(bkg, obj, grad, f32);
     case 1:
-      return hf::pick_1d_ng1(bkg, grad, f32);
+      return hf::pick_1d_ng1(bkg, obj, grad, f32);
     case 2:
-      return hf::pick_1d_ng2(bkg, grad, f32);
+      return hf::pick_1d_ng2(bkg, obj, grad, f32);
     case 3:
-      return hf::pick_1d_ng3(bkg, grad, f32);
+      return hf::pick_1d_ng3(bkg, obj, grad, f32);
     case 4:
-      return hf::pick_1d_ng4(bkg, grad, f32);
+      return hf::pick_1d_ng4(bkg, obj, grad, f32);
     default:
       return nullptr;
   }
 }
 
-// Grid for a grid-stride pass over nb bins in 4-bin chunks: at most
-// blocks_per_cu resident blocks per CU, and the chunks split as evenly as
-// that allows (every thread gets ceil or floor of the same count).
-int objective_grid(const hf_ctx* c, int64_t nb) {
-  const int64_t chunks = (nb + 3) / 4;
+// Grid for a grid-stride pass over nb bins in chunks of `chunk` bins: no more
+// blocks than can be resident at once (occupancy per CU x CUs), so the grid
+// runs in a single round, and the chunks split as evenly as that allows
+// (every thread gets ceil or floor of the same count).
+int objective_grid(const hf_ctx* c, int64_t nb, int chunk, int per_cu) {
+  const int64_t chunks = (nb + chunk - 1) / chunk;
   const int64_t per_block = hf::kBlock;
-  int64_t gmax = static_cast<int64_t>(c->num_cu) * c->blocks_per_cu;
+  int64_t gmax = static_cast<int64_t>(c->num_cu) * per_cu;
   if (gmax > kMaxGrid) gmax = kMaxGrid;
   if (gmax < 1) gmax = 1;
   int64_t need = (chunks + per_block - 1) / per_block;
@@ -191,7 +195,7 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   if (rc) return rc;
 
   hf::LaunchFn fn = two_d ? hf::pick_2d(grad, prec == HF_FP32_BIN)
-                          : pick_1d(m->n_gauss, bkg_code(m), grad, prec == HF_FP32_BIN);
+                          : pick_1d(m->n_gauss, bkg_code(m), obj, grad, prec == HF_FP32_BIN);
   if (!fn) return fail(c, HF_EUNSUPPORTED, "no kernel for this model");
 
   hf::NllArgs a{};
@@ -220,8 +224,17 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   a.part = c->part;
   a.part_flags = c->part_flags;
   a.ticket = c->ticket;
-  const int grid = objective_grid(c, a.nx * a.ny);
-  hipError_t e = fn(a, grid, stream);
+  a.log_lut = c->log_lut;
+  auto it = c->occupancy.find(fn);
+  if (it == c->occupancy.end()) {
+    int occ = 0;
+    hipError_t e = fn(a, 0, stream, &occ);
+    if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
+    it = c->occupancy.emplace(fn, occ < 1 ? 1 : occ).first;
+  }
+  const int per_cu = c->blocks_per_cu > 0 ? c->blocks_per_cu : it->second;
+  const int grid = objective_grid(c, a.nx * a.ny, two_d ? 4 : hf::kChunk, per_cu);
+  hipError_t e = fn(a, grid, stream, nullptr);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return HF_OK;
 }
@@ -248,7 +261,11 @@ HF_EXPORT int hf_ctx_create(hf_ctx** out, int device) {
     if (v >= 1 && v <= 32) c->blocks_per_cu = v;
   }
   const size_t part_bytes = sizeof(double) * kMaxNV * kMaxGrid;
-  if (hipMalloc(&c->part, part_bytes) != hipSuccess ||
+  double2 lut[hf::kLogLut];
+  for (int j = 0; j < hf::kLogLut; ++j) hf::log_lut_entry(j, &lut[j].x, &lut[j].y);
+  if (hipMalloc(&c->log_lut, sizeof lut) != hipSuccess ||
+      hipMemcpy(c->log_lut, lut, sizeof lut, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMalloc(&c->part, part_bytes) != hipSuccess ||
       hipMalloc(&c->part_flags, sizeof(int32_t) * kMaxGrid) != hipSuccess ||
       hipMalloc(&c->ticket, 256) != hipSuccess || hipMemset(c->ticket, 0, 256) != hipSuccess ||
       hf::fit_scratch_init(&c->fit) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
@@ -266,6 +283,7 @@ HF_EXPORT void hf_ctx_destroy(hf_ctx* c) {
   if (c->part) (void)hipFree(c->part);
   if (c->part_flags) (void)hipFree(c->part_flags);
   if (c->ticket) (void)hipFree(c->ticket);
+  if (c->log_lut) (void)hipFree(c->log_lut);
   hf::fit_scratch_free(&c->fit);
   if (cur >= 0 && cur != c->device) (void)hipSetDevice(cur);
   delete c;

@@ -1,0 +1,142 @@
+// chunk.hpp -- the per-bin forward/reverse sweep over a chunk of K
+// consecutive bins held by one thread.
+//
+// Gaussians on a uniform grid.  With z_k = z_0 + k dz (dz = h/s) the factor
+// e_k = exp(-z_k^2/2) obeys e_{k+1} = e_k r_k and r_{k+1} = r_k D, with
+// r_0 = exp(-dz z_0 - dz^2/2) and D = exp(-dz^2): two exps per Gaussian per
+// chunk instead of one per bin.  After k steps the relative error is about
+// k^2/2 ulp.  The recurrence is used only when K |dz| <= 1: then an e_0 that
+// underflows (|z_0| > 38.6) implies every e_k in the chunk is below 1e-300,
+// so nothing that matters is lost; r_0's exponent is clamped to +-700 so
+// that 0 * r_0 stays 0.  Otherwise each bin takes its own exp.
+//
+// Objective terms are branch-free (domain cases are only flagged), so the
+// compiler can interleave the K bins.
+#pragma once
+
+#include "device.hpp"
+#include "fastmath.hpp"
+
+namespace hf {
+
+// l(n, mu) and ubar = dl/dmu; returns true for a domain error.  Domain bins
+// are only flagged: the kernel then reports L = +inf and a NaN gradient, so
+// the common path carries no selects.  mu and n/mu are clamped to a tiny
+// positive value before the division and the log, which also makes the empty
+// bin (n = 0) come out exactly as l = mu, ubar = 1 (including mu = 0).
+template <int OBJ, bool F32BIN>
+__device__ __forceinline__ bool objective_t(double n, double mu, const double2* __restrict__ lut,
+                                            double& l, double& ub) {
+  constexpr double kTiny = 1e-300;
+  if constexpr (OBJ == OBJ_NEYMAN) {
+    const bool pos = n > 0.0;
+    const double inv = F32BIN ? rcp_hw32(fmax(n, kTiny)) : rcp_fast(fmax(n, kTiny));
+    const double d = mu - n;
+    const double di = pos ? d * inv : 0.0;
+    l = d * di;
+    ub = 2.0 * di;
+    return false;
+  } else if constexpr (OBJ == OBJ_PEARSON) {
+    const double inv = F32BIN ? rcp_hw32(fmax(mu, kTiny)) : rcp_fast(fmax(mu, kTiny));
+    const double d = n - mu;
+    const double r = n * inv;
+    l = d * d * inv;
+    ub = fma(-r, r, 1.0);
+    return !(mu > 0.0);
+  } else {
+    // Poisson, saturated: l = mu - n + n ln(n/mu) (n > 0), l = mu (n = 0)
+    const double r = div_fast<F32BIN>(n, fmax(mu, kTiny));
+    const double lg = log_lut<F32BIN>(fmax(r, kTiny), lut);
+    l = fma(n, lg, mu - n);
+    ub = 1.0 - r;
+    return (mu < 0.0) || (mu == 0.0 && n > 0.0);
+  }
+}
+
+template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN, bool RECUR, int K, int NV>
+__device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double2* __restrict__ lut,
+                                         double xs, const double (&n)[K], const double (&w)[K],
+                                         double (&acc)[NV], int& flags, double (&lk)[K]) {
+  using S = Shape1D<NG, BKG>;
+  constexpr int G1 = NG > 0 ? NG : 1;
+  double z0[G1], e[G1], r[G1];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    z0[g] = (xs - M.m[g]) * M.is[g];
+    if constexpr (RECUR) {
+      const double q0 = -0.5 * z0[g] * z0[g];
+      const double a0 = fmin(fmax(fma(-M.dz[g], z0[g], -0.5 * M.dz[g] * M.dz[g]), -700.0), 700.0);
+      e[g] = F32BIN ? exp_hw32(q0) : exp_fast(q0);
+      r[g] = F32BIN ? exp_hw32(a0) : exp_fast(a0);
+    }
+  }
+  const double t0 = (xs - M.tshift) * M.ta;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // ---- forward sweep ----
+    double z[G1], ek[G1], G[G1];
+    double mu = 0.0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      z[g] = fma(static_cast<double>(k), M.dz[g], z0[g]);
+      if constexpr (RECUR) {
+        ek[g] = e[g];
+      } else {
+        const double q = -0.5 * z[g] * z[g];
+        ek[g] = F32BIN ? exp_hw32(q) : exp_fast(q);
+      }
+      G[g] = M.A[g] * ek[g];
+      mu += G[g];
+    }
+    const double t = fma(static_cast<double>(k), M.dt, t0);
+    double E = 0.0;
+    if constexpr (BKG == BKG_EXP) {
+      const double a = fma(M.c[1], t, M.c[0]);
+      E = F32BIN ? exp_hw32(a) : exp_fast(a);
+      mu += E;
+    } else if constexpr (S::NB > 0) {
+      double b = M.c[S::NB - 1];
+#pragma unroll
+      for (int j = S::NB - 2; j >= 0; --j) b = fma(b, t, M.c[j]);
+      mu += b;
+    }
+    double l, ub;
+    const bool dom = objective_t<OBJ, F32BIN>(n[k], mu, lut, l, ub);
+    flags |= dom ? ST_DOMAIN : 0;
+    lk[k] = l;
+    acc[0] = fma(w[k], l, acc[0]);
+    if constexpr (GRAD) {
+      // ---- reverse sweep: mu_bar = w ubar (see bin_1d for the adjoint chain) ----
+      const double mb = w[k] * ub;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        acc[1 + 3 * g] = fma(mb, ek[g], acc[1 + 3 * g]);
+        const double zb = mb * G[g] * z[g];
+        acc[2 + 3 * g] += zb;
+        acc[3 + 3 * g] = fma(zb, z[g], acc[3 + 3 * g]);
+      }
+      constexpr int k0 = 1 + 3 * NG;
+      if constexpr (BKG == BKG_EXP) {
+        const double eb = mb * E;
+        acc[k0] += eb;
+        acc[k0 + 1] = fma(eb, t, acc[k0 + 1]);
+      } else if constexpr (S::NB > 0) {
+        double tj = mb;
+#pragma unroll
+        for (int j = 0; j < S::NB; ++j) {
+          acc[k0 + j] += tj;
+          tj *= t;
+        }
+      }
+    }
+    if constexpr (RECUR) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        e[g] *= r[g];
+        r[g] *= M.D[g];
+      }
+    }
+  }
+}
+
+}  // namespace hf

@@ -149,6 +149,12 @@ struct Model1D {
   double A[NG > 0 ? NG : 1], m[NG > 0 ? NG : 1], is[NG > 0 ? NG : 1];
   double c[S::NB > 0 ? S::NB : 1];
   double tshift, ta;  // t = (x - tshift) * ta; the subtraction first keeps t exact near 0
+  // Uniform-grid constants for a chunk of consecutive bins of width h:
+  // dz = h/s per Gaussian, D = exp(-dz^2), dt = h/t_scale; `recur` is set
+  // when every Gaussian satisfies K |dz| <= 1 (see chunk_1d).
+  double dz[NG > 0 ? NG : 1], D[NG > 0 ? NG : 1];
+  double dt;
+  bool recur;
 
   __device__ __forceinline__ void init(const double* __restrict__ th, double t_shift,
                                        double t_scale) {
@@ -162,6 +168,17 @@ struct Model1D {
     for (int j = 0; j < S::NB; ++j) c[j] = th[3 * NG + j];
     tshift = t_shift;
     ta = 1.0 / t_scale;
+  }
+
+  __device__ __forceinline__ void init_grid(double h, int K) {
+    recur = true;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      dz[g] = h * is[g];
+      D[g] = exp(-dz[g] * dz[g]);
+      recur = recur && (K * fabs(dz[g]) <= 1.0);
+    }
+    dt = h * ta;
   }
 
   // Factor applied to accumulated adjoint component k (0 = NLL) at the end:
@@ -368,26 +385,34 @@ __device__ __forceinline__ void store_relaxed(int* p, int v) {
 // over its threads, then the fixed block_sum tree) and returns true with the
 // grand totals in tot/totf.  That block also re-arms the ticket to 0, so the
 // counter needs clearing only once, when it is allocated.
+//
+// Ordering: the partials are written by lanes of wave 0 only (NV <= 64), and
+// the same wave issues an agent-scope release fence before lane 0 takes the
+// ticket, so one L2 write-back per block publishes them; only the last block
+// pays the acquire (L2 invalidate) before reading them.  A seq_cst fence in
+// every wave of every block costs an order of magnitude more on gfx950.
 template <int NV>
 __device__ __forceinline__ bool grid_sum(double (&v)[NV], int flags, double* __restrict__ part,
                                          int* __restrict__ part_flags, unsigned* ticket,
                                          double* tot, int* totf) {
+  static_assert(NV <= 64, "partials must be published by one wave");
   __shared__ double red[kWaves][NV];
   __shared__ int redf[kWaves];
   __shared__ int is_last;
   const int G = gridDim.x;
   block_sum<NV>(v, flags, tot, totf, red, redf);
-  if (threadIdx.x < NV) store_relaxed(&part[threadIdx.x * G + blockIdx.x], tot[threadIdx.x]);
-  if (threadIdx.x == 0) store_relaxed(&part_flags[blockIdx.x], *totf);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (t == static_cast<unsigned>(G - 1));
+  if (threadIdx.x < 64) {
+    if (threadIdx.x < NV) store_relaxed(&part[threadIdx.x * G + blockIdx.x], tot[threadIdx.x]);
+    if (threadIdx.x == 0) store_relaxed(&part_flags[blockIdx.x], *totf);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) {
+      const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      is_last = (t == static_cast<unsigned>(G - 1));
+    }
   }
   __syncthreads();
   if (!is_last) return false;
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   double a[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) a[k] = 0.0;

@@ -3,5 +3,7 @@
 #include "nll_kernels.hpp"
 
 namespace hf {
-LaunchFn pick_1d_ng2(int bkg, bool grad, bool f32) { return pick_1d_ng<2>(bkg, grad, f32); }
+LaunchFn pick_1d_ng2(int bkg, int obj, bool grad, bool f32) {
+  return pick_1d_ng<2>(bkg, obj, grad, f32);
+}
 }  // namespace hf

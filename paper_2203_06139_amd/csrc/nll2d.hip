@@ -95,9 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_nll_2d(NllArgs a) {
 }
 
 template <bool GRAD, bool F32BIN>
-hipError_t launch_2d(const NllArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_nll_2d<GRAD, F32BIN>), dim3(grid), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+hipError_t launch_2d(const NllArgs& a, int grid, hipStream_t s, int* occ) {
+  return launch_or_occupancy(k_nll_2d<GRAD, F32BIN>, a, grid, s, occ);
 }
 
 LaunchFn pick_2d(bool grad, bool f32) {

@@ -10,6 +10,7 @@
 // order reduction.  Bin centres are computed, never stored.
 #pragma once
 
+#include "chunk.hpp"
 #include "device.hpp"
 
 namespace hf {
@@ -34,9 +35,12 @@ struct NllArgs {
   double* part;
   int32_t* part_flags;
   unsigned* ticket;
+  const double2* log_lut;  // kLogLut entries, see log_lut_entry
 };
 
-using LaunchFn = hipError_t (*)(const NllArgs&, int grid, hipStream_t);
+// Launches a kernel variant with `grid` blocks; grid <= 0 instead returns,
+// through *occ, how many blocks of that kernel fit on one CU at once.
+using LaunchFn = hipError_t (*)(const NllArgs&, int grid, hipStream_t, int* occ);
 
 __device__ __forceinline__ void load_counts4(const NllArgs& a, int64_t i0, double (&n)[4]) {
   if (a.dtype == DT_U32) {
@@ -63,78 +67,178 @@ __device__ __forceinline__ double load_count1(const NllArgs& a, int64_t i) {
 }
 
 // Final stage shared by both kernels: the last block writes the outputs.
+// A non-finite theta makes every output NaN (and sets ST_NONFINITE), whatever
+// the clamped per-bin arithmetic produced; a domain error makes L = +inf and
+// the gradient NaN (the objective is not differentiable there).
 template <int NV, class M>
 __device__ __forceinline__ void write_outputs(const NllArgs& a, const M& model, const double* tot,
                                               int totf) {
   const int k = threadIdx.x;
+  const bool finite = all_finite(a.theta, a.P);
+  const double nan = __builtin_nan("");
+  const bool domain = (totf & ST_DOMAIN) != 0;
   if (k == 0) {
-    a.nll_out[0] = tot[0];
-    if (a.status_out) {
-      const int nf = all_finite(a.theta, a.P) ? 0 : ST_NONFINITE;
-      a.status_out[0] = totf | nf;
-    }
+    a.nll_out[0] = !finite ? nan : (domain ? __builtin_inf() : tot[0]);
+    if (a.status_out) a.status_out[0] = totf | (finite ? 0 : ST_NONFINITE);
   }
   if (NV > 1 && k >= 1 && k < NV) {
     const double seed = a.seed ? a.seed[0] : 1.0;
     const bool free = (a.free_mask == 0u) || ((a.free_mask >> (k - 1)) & 1u);
-    a.grad_out[k - 1] = free ? tot[k] * model.final_factor(k) * seed : 0.0;
+    a.grad_out[k - 1] =
+        (!finite || domain) ? nan : (free ? tot[k] * model.final_factor(k) * seed : 0.0);
   }
 }
 
-template <int NG, int BKG, bool GRAD, bool F32BIN>
-__global__ __launch_bounds__(kBlock) void k_nll_1d(NllArgs a) {
+// Bins per thread per step of the grid-stride loop (a multiple of 4: one
+// 16-byte load per 4 u32 counts), and the occupancy the register allocator
+// must leave room for (waves per SIMD).
+#ifndef HF_CHUNK
+#define HF_CHUNK 16
+#endif
+#ifndef HF_MIN_WAVES
+#define HF_MIN_WAVES 1
+#endif
+constexpr int kChunk = HF_CHUNK;
+constexpr int kMinWaves = HF_MIN_WAVES;
+static_assert(kChunk % 4 == 0, "chunk must be a multiple of 4 bins");
+
+// Counts of one chunk as loaded: 4-byte dtypes travel as raw 16-byte vectors
+// so the next chunk can be fetched while the current one is computed.
+struct ChunkRaw {
+  uint4 c[kChunk / 4];
+  float4 w[kChunk / 4];
+};
+
+template <bool SPEC>
+__device__ __forceinline__ void load_raw(const NllArgs& a, int64_t i0, ChunkRaw& r) {
+  const uint4* cp = reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(a.counts) + i0);
+#pragma unroll
+  for (int q = 0; q < kChunk / 4; ++q) r.c[q] = cp[q];
+  if (!SPEC && a.weights) {
+    const float4* wp = reinterpret_cast<const float4*>(a.weights + i0);
+#pragma unroll
+    for (int q = 0; q < kChunk / 4; ++q) r.w[q] = wp[q];
+  }
+}
+
+// SPEC: the counts are u32 and there are no weights (the common case, with
+// the conversions and weight products folded away); otherwise the dtype and
+// the weights are checked at run time.
+template <bool SPEC>
+__device__ __forceinline__ void unpack_raw(const NllArgs& a, const ChunkRaw& r, double (&n)[kChunk],
+                                           double (&w)[kChunk]) {
+#pragma unroll
+  for (int q = 0; q < kChunk / 4; ++q) {
+    if (SPEC || a.dtype == DT_U32) {
+      n[4 * q] = r.c[q].x;
+      n[4 * q + 1] = r.c[q].y;
+      n[4 * q + 2] = r.c[q].z;
+      n[4 * q + 3] = r.c[q].w;
+    } else {
+      n[4 * q] = __uint_as_float(r.c[q].x);
+      n[4 * q + 1] = __uint_as_float(r.c[q].y);
+      n[4 * q + 2] = __uint_as_float(r.c[q].z);
+      n[4 * q + 3] = __uint_as_float(r.c[q].w);
+    }
+    if (!SPEC && a.weights) {
+      w[4 * q] = r.w[q].x;
+      w[4 * q + 1] = r.w[q].y;
+      w[4 * q + 2] = r.w[q].z;
+      w[4 * q + 3] = r.w[q].w;
+    } else {
+      w[4 * q] = w[4 * q + 1] = w[4 * q + 2] = w[4 * q + 3] = 1.0;
+    }
+  }
+}
+
+template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN, int NV>
+__device__ __forceinline__ void chunk_step(const NllArgs& a, const Model1D<NG, BKG>& M,
+                                           const double2* lut, int64_t i0, const double (&n)[kChunk],
+                                           const double (&w)[kChunk], double seed,
+                                           double (&acc)[NV], int& flags) {
+  const double xs = fma(static_cast<double>(i0), a.hx, a.x0);
+  double l[kChunk];
+  if (M.recur)
+    chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, true>(M, lut, xs, n, w, acc, flags, l);
+  else
+    chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, false>(M, lut, xs, n, w, acc, flags, l);
+  if (a.grad_w_out) {
+#pragma unroll
+    for (int q = 0; q < kChunk / 4; ++q) {
+      float4 o;
+      o.x = static_cast<float>(seed * l[4 * q]);
+      o.y = static_cast<float>(seed * l[4 * q + 1]);
+      o.z = static_cast<float>(seed * l[4 * q + 2]);
+      o.w = static_cast<float>(seed * l[4 * q + 3]);
+      reinterpret_cast<float4*>(a.grad_w_out + i0)[q] = o;
+    }
+  }
+}
+
+// Grid-stride loop over the full chunks of 4-byte counts, with the next chunk
+// loaded while the current one is computed.
+template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN, bool SPEC, int NV>
+__device__ __forceinline__ void stream_chunks(const NllArgs& a, const Model1D<NG, BKG>& M,
+                                              const double2* lut, int64_t nfull, int64_t tid,
+                                              int64_t stride, double seed, double (&acc)[NV],
+                                              int& flags) {
+  ChunkRaw nxt;
+  if (tid < nfull) load_raw<SPEC>(a, tid * kChunk, nxt);
+  for (int64_t c = tid; c < nfull; c += stride) {
+    const ChunkRaw cur = nxt;
+    if (c + stride < nfull) load_raw<SPEC>(a, (c + stride) * kChunk, nxt);
+    double n[kChunk], w[kChunk];
+    unpack_raw<SPEC>(a, cur, n, w);
+    chunk_step<NG, BKG, OBJ, GRAD, F32BIN>(a, M, lut, c * kChunk, n, w, seed, acc, flags);
+  }
+}
+
+template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN>
+__global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_1d(NllArgs a) {
   using S = Shape1D<NG, BKG>;
   constexpr int NV = GRAD ? S::P + 1 : 1;
+  __shared__ double2 lut[kLogLut];
+  if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
   Model1D<NG, BKG> M;
   M.init(a.theta, a.t_shift, a.t_scale);
+  M.init_grid(a.hx, kChunk);
+  if constexpr (OBJ == OBJ_POISSON) __syncthreads();
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
-  const int obj = a.obj;
   const double seed = (a.grad_w_out && a.seed) ? a.seed[0] : 1.0;
   const int64_t nb = a.nx;
-  const int64_t nfull = nb >> 2;
+  const int64_t nfull = nb / kChunk;
   const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
 
-  for (int64_t c = tid; c < nfull; c += stride) {
-    const int64_t i0 = c << 2;
-    double n[4];
-    load_counts4(a, i0, n);
-    double w[4] = {1.0, 1.0, 1.0, 1.0};
-    if (a.weights) {
-      const float4 wv = *reinterpret_cast<const float4*>(a.weights + i0);
-      w[0] = wv.x;
-      w[1] = wv.y;
-      w[2] = wv.z;
-      w[3] = wv.w;
-    }
-    const double xb = fma(static_cast<double>(i0), a.hx, a.x0);
-    double l[4];
+  if (a.dtype == DT_U32 && !a.weights) {
+    stream_chunks<NG, BKG, OBJ, GRAD, F32BIN, true>(a, M, lut, nfull, tid, stride, seed, acc, flags);
+  } else if (a.dtype != DT_F64) {
+    stream_chunks<NG, BKG, OBJ, GRAD, F32BIN, false>(a, M, lut, nfull, tid, stride, seed, acc, flags);
+  } else {
+    for (int64_t c = tid; c < nfull; c += stride) {
+      const int64_t i0 = c * kChunk;
+      double n[kChunk], w[kChunk];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double x = fma(static_cast<double>(k), a.hx, xb);
-      l[k] = bin_1d<NG, BKG, GRAD, F32BIN>(M, obj, x, n[k], w[k], acc, flags);
-    }
-    if (a.grad_w_out) {
-      float4 o;
-      o.x = static_cast<float>(seed * l[0]);
-      o.y = static_cast<float>(seed * l[1]);
-      o.z = static_cast<float>(seed * l[2]);
-      o.w = static_cast<float>(seed * l[3]);
-      *reinterpret_cast<float4*>(a.grad_w_out + i0) = o;
+      for (int k = 0; k < kChunk; ++k) {
+        n[k] = static_cast<const double*>(a.counts)[i0 + k];
+        w[k] = a.weights ? static_cast<double>(a.weights[i0 + k]) : 1.0;
+      }
+      chunk_step<NG, BKG, OBJ, GRAD, F32BIN>(a, M, lut, i0, n, w, seed, acc, flags);
     }
   }
-  // ragged tail: at most 3 bins, one per thread of the first threads
-  const int64_t tail = nb - (nfull << 2);
+  // ragged tail: fewer than kChunk bins, one per thread of the first threads
+  const int64_t tail = nb - nfull * kChunk;
   if (tid < tail) {
-    const int64_t i = (nfull << 2) + tid;
-    const double n = load_count1(a, i);
-    const double w = a.weights ? static_cast<double>(a.weights[i]) : 1.0;
-    const double x = fma(static_cast<double>(i), a.hx, a.x0);
-    const double l = bin_1d<NG, BKG, GRAD, F32BIN>(M, obj, x, n, w, acc, flags);
-    if (a.grad_w_out) a.grad_w_out[i] = static_cast<float>(seed * l);
+    const int64_t i = nfull * kChunk + tid;
+    const double n[1] = {load_count1(a, i)};
+    const double w[1] = {a.weights ? static_cast<double>(a.weights[i]) : 1.0};
+    double l[1];
+    chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, false>(M, lut, fma(static_cast<double>(i), a.hx, a.x0),
+                                                  n, w, acc, flags, l);
+    if (a.grad_w_out) a.grad_w_out[i] = static_cast<float>(seed * l[0]);
   }
 
   __shared__ double tot[NV];
@@ -143,45 +247,65 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d(NllArgs a) {
     write_outputs<NV>(a, M, tot, totf);
 }
 
-template <int NG, int BKG, bool GRAD, bool F32BIN>
-hipError_t launch_1d(const NllArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_nll_1d<NG, BKG, GRAD, F32BIN>), dim3(grid), dim3(kBlock), 0, s, a);
+template <class K>
+hipError_t launch_or_occupancy(K kernel, const NllArgs& a, int grid, hipStream_t s, int* occ) {
+  if (grid <= 0) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kernel, kBlock, 0);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-template <int NG, int BKG>
+template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN>
+hipError_t launch_1d(const NllArgs& a, int grid, hipStream_t s, int* occ) {
+  return launch_or_occupancy(k_nll_1d<NG, BKG, OBJ, GRAD, F32BIN>, a, grid, s, occ);
+}
+
+template <int NG, int BKG, int OBJ>
 LaunchFn pick_grad_prec(bool grad, bool f32) {
-  if (grad) return f32 ? &launch_1d<NG, BKG, true, true> : &launch_1d<NG, BKG, true, false>;
-  return f32 ? &launch_1d<NG, BKG, false, true> : &launch_1d<NG, BKG, false, false>;
+  if (grad) return f32 ? &launch_1d<NG, BKG, OBJ, true, true> : &launch_1d<NG, BKG, OBJ, true, false>;
+  return f32 ? &launch_1d<NG, BKG, OBJ, false, true> : &launch_1d<NG, BKG, OBJ, false, false>;
+}
+
+template <int NG, int BKG>
+LaunchFn pick_obj(int obj, bool grad, bool f32) {
+  switch (obj) {
+    case OBJ_NEYMAN:
+      return pick_grad_prec<NG, BKG, OBJ_NEYMAN>(grad, f32);
+    case OBJ_PEARSON:
+      return pick_grad_prec<NG, BKG, OBJ_PEARSON>(grad, f32);
+    case OBJ_POISSON:
+      return pick_grad_prec<NG, BKG, OBJ_POISSON>(grad, f32);
+    default:
+      return nullptr;
+  }
 }
 
 template <int NG>
-LaunchFn pick_1d_ng(int bkg, bool grad, bool f32) {
+LaunchFn pick_1d_ng(int bkg, int obj, bool grad, bool f32) {
   switch (bkg) {
     case BKG_NONE:
       if constexpr (NG == 0) return nullptr;
-      else return pick_grad_prec<NG, BKG_NONE>(grad, f32);
+      else return pick_obj<NG, BKG_NONE>(obj, grad, f32);
     case 0:
-      return pick_grad_prec<NG, 0>(grad, f32);
+      return pick_obj<NG, 0>(obj, grad, f32);
     case 1:
-      return pick_grad_prec<NG, 1>(grad, f32);
+      return pick_obj<NG, 1>(obj, grad, f32);
     case 2:
-      return pick_grad_prec<NG, 2>(grad, f32);
+      return pick_obj<NG, 2>(obj, grad, f32);
     case 3:
-      return pick_grad_prec<NG, 3>(grad, f32);
+      return pick_obj<NG, 3>(obj, grad, f32);
     case BKG_EXP:
-      return pick_grad_prec<NG, BKG_EXP>(grad, f32);
+      return pick_obj<NG, BKG_EXP>(obj, grad, f32);
     default:
       return nullptr;
   }
 }
 
 // Defined in nll1d_ng{0..4}.hip and nll2d.hip.
-LaunchFn pick_1d_ng0(int bkg, bool grad, bool f32);
-LaunchFn pick_1d_ng1(int bkg, bool grad, bool f32);
-LaunchFn pick_1d_ng2(int bkg, bool grad, bool f32);
-LaunchFn pick_1d_ng3(int bkg, bool grad, bool f32);
-LaunchFn pick_1d_ng4(int bkg, bool grad, bool f32);
+LaunchFn pick_1d_ng0(int bkg, int obj, bool grad, bool f32);
+LaunchFn pick_1d_ng1(int bkg, int obj, bool grad, bool f32);
+LaunchFn pick_1d_ng2(int bkg, int obj, bool grad, bool f32);
+LaunchFn pick_1d_ng3(int bkg, int obj, bool grad, bool f32);
+LaunchFn pick_1d_ng4(int bkg, int obj, bool grad, bool f32);
 LaunchFn pick_2d(bool grad, bool f32);
 
 }  // namespace hf

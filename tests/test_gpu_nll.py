@@ -127,7 +127,7 @@ def test_seed_free_mask_and_status(hf, orc):
     refb = orc.nll_grad(orc_model(orc, spec), 2, c["counts"], bad, r)
     nll, grad, _, st = gpu_eval(hf, spec, c["counts"], bad, r, 2, 0)
     assert refb.status & 1 and st & hf.ST_DOMAIN and nll == math.inf
-    assert np.all(np.abs(grad - refb.grad) <= 1e-10 * refb.scales[1:])
+    assert np.all(np.isnan(grad)) and np.all(np.isnan(refb.grad))
     # non-finite theta
     nanth = np.array(c["theta_eval"])
     nanth[1] = math.nan

@@ -317,6 +317,7 @@ def test_domain_and_nonfinite(orc):
     # Poisson with mu <= 0 and n > 0: +inf, status bit 0
     res = orc.nll_grad(M, 2, n, [-1.0], r)
     assert res.nll == math.inf and res.status & orc.ST_DOMAIN
+    assert np.all(np.isnan(res.grad))  # not differentiable at +inf
     # Poisson with mu = 0: the empty bin gives 0, occupied bins are domain errors
     res = orc.nll_grad(M, 2, np.zeros(3), [0.0], r)
     assert res.nll == 0.0 and res.status == 0 and res.grad[0] == 3.0
