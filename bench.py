@@ -17,6 +17,8 @@ one full histogram, repeated for ~10 s.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +43,33 @@ FLOPS_BASIC = 49
 FLOPS_EXP, FLOPS_LOG, FLOPS_DIV = 26, 30, 10
 FLOPS_PER_BIN = FLOPS_BASIC + 2 * FLOPS_EXP + FLOPS_LOG + FLOPS_DIV
 BYTES_PER_BIN = 4  # one u32 count per bin
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "nll_grad_1e7_traffic.json")
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources the timed kernel is built from; HBM traffic
+    measured with rocprofv3 counters is only reported for the same sources."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_06139_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision, objective):
+    """Bytes per launch (fetch + write) from the committed counter summary,
+    or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    key = "%s/%s" % (precision, objective)
+    if t.get("source_hash") != kernel_source_hash() or key not in t.get("per_launch_bytes", {}):
+        return None
+    return t["per_launch_bytes"][key]
 
 
 def log(msg):
@@ -85,6 +114,9 @@ def main():
     ap.add_argument("--objective", choices=["poisson", "neyman", "pearson"], default="poisson")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after timing, copy a MIB-sized device buffer 4 times (a plain "
+                         "copy of known size to scale HBM counters against)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the histogram objective is not sharded across GPUs "
@@ -125,31 +157,36 @@ def main():
         step(k)
     torch.cuda.synchronize()
 
-    per_graph = NCOPIES * 4
-    graph = None
+    # K steps = full replays of a 32-step graph + one replay of a remainder graph
+    steps = args.steps
+    per_graph = min(NCOPIES * 4, steps)
+    graphs = []  # (graph, replays)
     if not args.no_graph:
-        graph = torch.cuda.CUDAGraph()
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            with torch.cuda.graph(graph, stream=s):
-                for k in range(per_graph):
-                    step(k)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        for count, replays in ((per_graph, steps // per_graph), (steps % per_graph, 1)):
+            if count == 0 or replays == 0:
+                continue
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(g, stream=side):
+                    for k in range(count):
+                        step(k)
+            graphs.append((g, replays))
         torch.cuda.synchronize()
-        graph.replay()  # untimed replay
+        for g, _ in graphs:
+            g.replay()  # untimed replay
         torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    steps = args.steps
-    if graph is not None:
-        steps = max(per_graph, (steps + per_graph - 1) // per_graph * per_graph)
     torch.cuda.synchronize()
     t_host = time.perf_counter()
     ev0.record(stream)
-    if graph is not None:
-        for _ in range(steps // per_graph):
-            graph.replay()
+    if graphs:
+        for g, replays in graphs:
+            for _ in range(replays):
+                g.replay()
     else:
         for k in range(steps):
             step(k)
@@ -180,12 +217,22 @@ def main():
                              "background (10 parameters), %s NLL + reverse-mode gradient, "
                              "%s bins, 8 rotating histograms" % (args.objective, args.precision),
                     nbins=NBINS, params=P, objective=args.objective,
-                    precision=args.precision, graph=graph is not None),
+                    precision=args.precision, graph=bool(graphs)),
     )
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 4 x %d MiB device-to-device" % args.copy_calibration)
     flops = FLOPS_PER_BIN * NBINS
     achieved = flops / (ms_per_step * 1e-3) / 1e12
+    traffic = measured_traffic(args.precision, args.objective)
     result["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VEC_PEAK_TFLOPS,
-                              unit="TFLOP/s", frac=achieved / FP64_VEC_PEAK_TFLOPS, traffic=None,
+                              unit="TFLOP/s", frac=achieved / FP64_VEC_PEAK_TFLOPS, traffic=traffic,
                               flops_per_bin=FLOPS_PER_BIN,
                               hbm_gbs=BYTES_PER_BIN * NBINS / (ms_per_step * 1e-3) / 1e9,
                               hbm_frac=BYTES_PER_BIN * NBINS / (ms_per_step * 1e-3) / 1e9 /
