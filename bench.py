@@ -114,6 +114,10 @@ def main():
     ap.add_argument("--objective", choices=["poisson", "neyman", "pearson"], default="poisson")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits"], default="large1d",
+                    help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
+                         "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
+                         "fit_batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after timing, copy a MIB-sized device buffer 4 times (a plain "
                          "copy of known size to scale HBM counters against)")
@@ -132,6 +136,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "hist2d":
+        return bench_hist2d(args, hf, datagen, np, torch, dev)
+    if args.workload == "fits":
+        return bench_fits(args, hf, datagen, np, torch, dev)
     obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
 
@@ -251,6 +259,107 @@ def main():
         result["parity"] = dict(rel_err_nll=err_nll, rel_err_grad=err_grad, tol=tol,
                                 ok=bool(err_nll <= tol and err_grad <= tol))
     print(json.dumps(result), flush=True)
+
+
+def time_graph(torch, step, steps):
+    """Time exactly `steps` calls of step(k) replayed from HIP graphs; returns ms per call."""
+    per_graph = min(32, steps)
+    graphs = []
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for count, replays in ((per_graph, steps // per_graph), (steps % per_graph, 1)):
+        if count == 0 or replays == 0:
+            continue
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                for k in range(count):
+                    step(k)
+        graphs.append((g, replays))
+    torch.cuda.synchronize()
+    for g, _ in graphs:
+        g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for g, replays in graphs:
+        for _ in range(replays):
+            g.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def bench_hist2d(args, hf, datagen, np, torch, dev):
+    """2048^2 weighted Poisson NLL + theta gradient + per-bin weight gradient
+    (the backward of the differentiable objective), 12 bytes per bin."""
+    c = datagen.hist2d_case()
+    h = hf.make_hist(c["counts"], (0.0, 1.0), (0.0, 1.0), weights=c["weights"], device=dev)
+    th = torch.as_tensor(c["theta_eval"], dtype=torch.float64, device=dev)
+    m = hf.Model(hf.GAUSS2D)
+    seed = torch.ones(1, dtype=torch.float64, device=dev)
+    nll = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(7, dtype=torch.float64, device=dev)
+    gw = torch.empty(c["counts"].shape, dtype=torch.float32, device=dev)
+    prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
+
+    def step(k):
+        hf.nll_grad(h, m, th, objective=hf.POISSON, precision=prec, seed=seed, nll_out=nll,
+                    grad_out=g, grad_w_out=gw)
+
+    for k in range(args.warmup):
+        step(k)
+    ms = time_graph(torch, step, args.steps)
+    nb = c["counts"].size
+    print(json.dumps(dict(metric="bins*(NLL+grad+grad_w)/s", value=nb / (ms * 1e-3), unit="bins/s",
+                          n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
+                          higher_is_better=True, scaling="weak", vs_baseline=None,
+                          dtype="f64" if prec == hf.FP64 else "f32-bin/f64-acc",
+                          data="synthetic",
+                          config=dict(workload="2D histogram 2048x2048, correlated Gaussian + "
+                                               "constant (7 parameters), f32 weights, weighted "
+                                               "Poisson NLL + gradient + weight gradient",
+                                      nbins=nb, precision=args.precision),
+                          hbm_gbs=12 * nb / (ms * 1e-3) / 1e9)), flush=True)
+
+
+def bench_fits(args, hf, datagen, np, torch, dev):
+    """4096 histograms (256..65536 bins, Gauss + exponential background) fitted
+    in one fit_batch launch; fits/s counts fits whose final NLL agrees with the
+    FP64-bin fit from the same start within 1e-6."""
+    c = datagen.batch_case()
+    B = len(c["nbins"])
+    rng = np.random.default_rng(33)
+    th0 = c["theta_true"].copy()
+    th0[:, 0] *= 1 + 0.05 * rng.standard_normal(B)
+    th0[:, 1] += 0.3 * th0[:, 2] * rng.standard_normal(B)
+    th0[:, 2] *= 1 + 0.05 * rng.standard_normal(B)
+    counts = torch.from_numpy(c["counts"].view(np.int32)).to(dev)
+    off = torch.as_tensor(c["offsets"], device=dev)
+    rg = torch.as_tensor(c["ranges"], device=dev)
+    t0 = torch.as_tensor(th0, device=dev)
+    m = hf.Model.from_spec(c["spec"])
+    prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
+    kw = dict(objective=hf.POISSON, precision=prec, polish_edm=1e-3 if prec == hf.FP32_BIN else 0.0)
+    ref = hf.fit_batch(counts, off, rg, m, t0, objective=hf.POISSON, precision=hf.FP64)
+    out = hf.fit_batch(counts, off, rg, m, t0, **kw)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 5))
+    ms = time_graph(torch, lambda k: hf.fit_batch(counts, off, rg, m, t0, out=out, **kw), steps)
+    ok = ((out.status == 0) & (ref.status == 0) & ((out.nll - ref.nll).abs() < 1e-6)).sum().item()
+    print(json.dumps(dict(metric="fits/s at |dNLL|<1e-6", value=ok / (ms * 1e-3), unit="fits/s",
+                          n_gpus=1, steps=steps, warmup=1, ms_per_step=ms, higher_is_better=True,
+                          scaling="weak", vs_baseline=None,
+                          dtype="f64" if prec == hf.FP64 else "f32-bin/f64-acc",
+                          data="synthetic",
+                          config=dict(workload="4096 1D histograms, 256..65536 bins (log-uniform), "
+                                               "Gauss + exponential background, Poisson, one "
+                                               "fit_batch launch", histograms=B,
+                                      total_bins=int(c["offsets"][-1]), agreeing=ok,
+                                      mean_iters=float(out.iters.float().mean().item()),
+                                      mean_evals=float(out.nevals.float().mean().item()),
+                                      precision=args.precision))), flush=True)
 
 
 if __name__ == "__main__":

@@ -10,7 +10,9 @@ bin for the correlated 2D Gaussian).  That is how a real histogram is filled
 (paper, sec. 4, Fig. 2a fills its histogram from the function by sampling),
 and it differs from the bin-centre value the method evaluates by O(h^2/s^2).
 
-Every generator takes an explicit seed and uses numpy's PCG64.
+Every generator takes an explicit seed and uses numpy's PCG64, except
+batch_case_device, which draws the same distribution with seeded torch
+generators on a device (for training sets of ~1e6 histograms).
 
 Model descriptors are plain dicts {kind, n_gauss, poly_degree, t_shift,
 t_scale}; kind 1 = Gaussians + polynomial in t = (x - t_shift)/t_scale,
@@ -223,3 +225,41 @@ def random_1d_case(spec, nbins, lo, hi, theta, seed, rel=0.02):
     counts = poisson_counts(lam, rng)
     return dict(spec=spec, counts=counts, range=(lo, hi), theta_true=np.asarray(theta, float),
                 theta_eval=perturb(theta, rel, rng))
+
+
+def batch_case_device(seed, B, nbins=4096, device="cuda"):
+    """The batched-fit distribution (see batch_case) with a fixed bin count,
+    generated on a torch device: parameters from a seeded CPU generator,
+    bin-integrated intensities and Poisson draws on the device (seeded).
+    Returns int32 counts (u32 values) of shape [B * nbins], int64 offsets,
+    f64 ranges [B, 2] and the generating theta [B, 5] (CPU float64)."""
+    import torch
+
+    g = torch.Generator(device="cpu").manual_seed(seed)
+
+    def logu(a, b):
+        return torch.exp(torch.empty(B, dtype=torch.float64).uniform_(math.log(a), math.log(b),
+                                                                       generator=g))
+
+    A = logu(1e2, 1e4)
+    m = torch.empty(B, dtype=torch.float64).uniform_(0.0, 1.0, generator=g)
+    s = torch.empty(B, dtype=torch.float64).uniform_(0.01, 0.05, generator=g)
+    bk0, bk1 = logu(10.0, 1000.0), logu(10.0, 1000.0)
+    theta = torch.stack([A, m, s, torch.log(bk0), torch.log(bk1 / bk0)], dim=1)
+    th = theta.to(device)
+    e = torch.linspace(0.0, 1.0, nbins + 1, dtype=torch.float64, device=device)
+    a, b = e[:-1][None, :], e[1:][None, :]
+    h = 1.0 / nbins
+    za = (a - th[:, 1:2]) / th[:, 2:3]
+    zb = (b - th[:, 1:2]) / th[:, 2:3]
+    right = za >= 0
+    p = torch.where(right, torch.special.ndtr(-za) - torch.special.ndtr(-zb),
+                    torch.special.ndtr(zb) - torch.special.ndtr(za))
+    lam = th[:, 0:1] * th[:, 2:3] * math.sqrt(2.0 * math.pi) * p / h
+    b1 = th[:, 4:5]
+    lam = lam + torch.exp(th[:, 3:4] + b1 * a) * torch.expm1(b1 * h) / (b1 * h)
+    gd = torch.Generator(device=device).manual_seed(seed + 7919)
+    counts = torch.poisson(lam, generator=gd).to(torch.int32).reshape(-1)
+    offsets = torch.arange(B + 1, dtype=torch.int64) * nbins
+    ranges = torch.tensor([[0.0, 1.0]], dtype=torch.float64).repeat(B, 1)
+    return counts, offsets, ranges, theta

@@ -199,6 +199,86 @@ int fit_batch(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t counts_
               double* theta_out, double* nll_out, int32_t* status, int32_t* iters,
               int32_t* nevals, hf_stream_t stream);
 
+
+/* ------------------------------------------------------------------------
+ * Learned initialiser: a dense GELU network 256 -> 512 -> 512 -> 512 -> 5
+ * that predicts fit starting parameters of the Gauss + exponential model
+ * from a 256-bin rebinned, log-normalised histogram.  It is trained on the
+ * results of plain fits (fit_batch from hf_default_starts) and used as the
+ * start of the same fitter, with the plain start as fallback.  Dense layers
+ * run on BF16 MFMA with FP32 accumulation; master weights, Adam moments and
+ * the loss are FP32.
+ *
+ * Flat FP32 parameter layout (offsets in floats, row-major [out][in]):
+ *   W1[512][256] b1[512] W2[512][512] b2[512] W3[512][512] b3[512]
+ *   W4[32][512] b4[32]; rows 5..31 of W4 and b4[5..31] are padding and must
+ *   be zero (they then stay zero).  Total hf_mlp_nparams() floats.
+ * Target space (per fit, 5 values): (m, ln|s|, ln A, b0, b1), standardised by
+ * per-column mean and standard deviation.
+ * Batch sizes must be multiples of 64.
+ * ---------------------------------------------------------------------- */
+enum { HF_MLP_IN = 256, HF_MLP_HIDDEN = 512, HF_MLP_OUT = 5, HF_MLP_OUT_PAD = 32 };
+
+int64_t hf_mlp_nparams(void);
+/* Device scratch a forward or training step of `batch` rows needs (bytes). */
+int64_t hf_mlp_workspace_bytes(int32_t batch);
+
+/* Rebins histogram b of counts_concat (offsets as in fit_batch) to 256 coarse
+ * bins -- fine bin i goes to coarse bin floor((i + 1/2) 256 / nbins) -- and
+ * writes out[b][j] = (log1p(c_j / k_j) - in_mean) / in_std, with c_j the
+ * summed counts and k_j the number of fine bins of coarse bin j (0 if none).
+ * out: device f32[B][256].                                                */
+int hf_rebin_lognorm(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t counts_dtype,
+                     const int64_t* offsets, float in_mean, float in_std, float* out,
+                     hf_stream_t stream);
+
+/* The plain method's starting point for one Gaussian + exp(b0 + b1 t)
+ * (model: HF_GAUSS_EXP, n_gauss = 1), per histogram of a batch laid out as
+ * in fit_batch:
+ *   background: mean counts of the first and last 4% of the bins (at least
+ *     one bin, floored at 1), an exponential through the two block centres;
+ *   peak: the largest integer excess E_i = window sum - rint((2W+1) x the
+ *     linear interpolation of the two edge means), window 2W+1 bins with
+ *     W = max(1, nbins/256), lowest index on ties; A = max(E/(2W+1), 1);
+ *   width: the excess walked outwards from the peak until 2 E < E_max gives
+ *     the FWHM; s = FWHM/2.3548 clamped to [0.005, 0.1] of the range.
+ * theta0: device f64[B][5] (A, m, s, b0, b1).                              */
+int hf_default_starts(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t counts_dtype,
+                      const int64_t* offsets, const double* ranges, const hf_model* model,
+                      double* theta0, hf_stream_t stream);
+
+/* Per-column mean and population standard deviation of x[n][cols] (device
+ * f32), summed in FP64 in a fixed order; mean, std: device f32[cols].       */
+int hf_column_stats(hf_ctx* ctx, int64_t n, int32_t cols, const float* x, float* mean, float* std,
+                    hf_stream_t stream);
+
+/* theta (device f64[B][5], Gauss + exp model) -> standardised targets
+ * (device f32[B][5]): ((m, ln|s|, ln A, b0, b1) - mean)/std.  With mean = 0
+ * and std = 1 it gives the raw target values (for hf_column_stats).      */
+int hf_theta_to_target(hf_ctx* ctx, int32_t B, const double* theta, const float* mean,
+                       const float* std, float* target, hf_stream_t stream);
+/* Network outputs (device f32[B][32], first 5 columns) -> theta (f64[B][5]). */
+int hf_target_to_theta(hf_ctx* ctx, int32_t B, const float* y, const float* mean,
+                       const float* std, double* theta, hf_stream_t stream);
+
+/* Forward pass: y = network(x).  params: device f32[hf_mlp_nparams()];
+ * x: device f32[batch][256]; y: device f32[batch][32] (columns 5..31 are the
+ * padding outputs); workspace: device, hf_mlp_workspace_bytes(batch).      */
+int hf_mlp_forward(hf_ctx* ctx, int32_t batch, const float* params, const float* x, float* y,
+                   void* workspace, hf_stream_t stream);
+
+/* One AdamW step (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay
+ * wd) on the mean squared error over the 5 target columns:
+ * loss = sum (y - target)^2 / (5 batch).  params, adam_m, adam_v: device
+ * f32[hf_mlp_nparams()], updated in place; step: 1-based step count (bias
+ * correction); grads: device f32[hf_mlp_nparams()] receives the gradient of
+ * this step; loss_out: device f32[1].  Rounding points: x, weights,
+ * activations and output/hidden adjoints are rounded to BF16 (nearest even)
+ * before each product; products accumulate in FP32.                      */
+int hf_mlp_train_step(hf_ctx* ctx, int32_t batch, float* params, float* adam_m, float* adam_v,
+                      int32_t step, float lr, float wd, const float* x, const float* target,
+                      float* grads, float* loss_out, void* workspace, hf_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -110,7 +110,21 @@ def load():
     L.fit_batch.argtypes = [vp, i32, vp, i32, vp, vp, ctypes.POINTER(HfModel), i32, i32, vp,
                             ctypes.POINTER(HfFitOpts), vp, vp, vp, vp, vp, vp]
     L.fit_batch.restype = ctypes.c_int
-    _ = i64
+    f32 = ctypes.c_float
+    L.hf_mlp_nparams.argtypes = []
+    L.hf_mlp_nparams.restype = i64
+    L.hf_mlp_workspace_bytes.argtypes = [i32]
+    L.hf_mlp_workspace_bytes.restype = i64
+    L.hf_rebin_lognorm.argtypes = [vp, i32, vp, i32, vp, f32, f32, vp, vp]
+    L.hf_default_starts.argtypes = [vp, i32, vp, i32, vp, vp, ctypes.POINTER(HfModel), vp, vp]
+    L.hf_column_stats.argtypes = [vp, i64, i32, vp, vp, vp, vp]
+    L.hf_theta_to_target.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.hf_target_to_theta.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.hf_mlp_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.hf_mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp, vp, vp]
+    for fn in (L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
+               L.hf_target_to_theta, L.hf_mlp_forward, L.hf_mlp_train_step):
+        fn.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -307,3 +321,102 @@ def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=PO
                           _ptr(out.iters), _ptr(out.nevals), _stream(dev))
     _check(rc, ctx)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Learned initialiser (see include/histfit.h for the definitions)
+# ---------------------------------------------------------------------------
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_OUT_PAD = 256, 512, 5, 32
+
+
+def mlp_nparams() -> int:
+    return int(load().hf_mlp_nparams())
+
+
+def mlp_workspace(batch: int, device):
+    import torch
+    n = int(load().hf_mlp_workspace_bytes(batch))
+    if n < 0:
+        raise ValueError("batch must be a positive multiple of 64")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _batch_args(counts_concat, offsets):
+    import torch
+    c = counts_concat
+    off = offsets if isinstance(offsets, torch.Tensor) and offsets.device == c.device else \
+        _dev_tensor(offsets, torch.int64, c.device, "offsets")
+    return c, off, off.numel() - 1
+
+
+def rebin_lognorm(counts_concat, offsets, in_mean=0.0, in_std=1.0, out=None):
+    import torch
+    c, off, B = _batch_args(counts_concat, offsets)
+    ctx = context(c.device.index)
+    out = torch.empty(B, MLP_IN, dtype=torch.float32, device=c.device) if out is None else out
+    _check(load().hf_rebin_lognorm(ctx, B, _ptr(c), _dtype_code(c), _ptr(off), float(in_mean),
+                                   float(in_std), _ptr(out), _stream(c.device)), ctx)
+    return out
+
+
+def default_starts(counts_concat, offsets, ranges, model: Model, out=None):
+    import torch
+    c, off, B = _batch_args(counts_concat, offsets)
+    ctx = context(c.device.index)
+    rg = _dev_tensor(ranges, torch.float64, c.device, "ranges")
+    out = torch.empty(B, 5, dtype=torch.float64, device=c.device) if out is None else out
+    _check(load().hf_default_starts(ctx, B, _ptr(c), _dtype_code(c), _ptr(off), _ptr(rg),
+                                    ctypes.byref(model.c()), _ptr(out), _stream(c.device)), ctx)
+    return out
+
+
+def column_stats(x):
+    """Per-column mean and standard deviation of a device f32 [n, cols] tensor."""
+    import torch
+    x = _dev_tensor(x, torch.float32, x.device, "x")
+    n, cols = x.shape
+    ctx = context(x.device.index)
+    mean = torch.empty(cols, dtype=torch.float32, device=x.device)
+    std = torch.empty(cols, dtype=torch.float32, device=x.device)
+    _check(load().hf_column_stats(ctx, n, cols, _ptr(x), _ptr(mean), _ptr(std), _stream(x.device)),
+           ctx)
+    return mean, std
+
+
+def theta_to_target(theta, mean, std, out=None):
+    import torch
+    B = theta.shape[0]
+    ctx = context(theta.device.index)
+    out = torch.empty(B, 5, dtype=torch.float32, device=theta.device) if out is None else out
+    _check(load().hf_theta_to_target(ctx, B, _ptr(theta.contiguous()), _ptr(mean), _ptr(std),
+                                     _ptr(out), _stream(theta.device)), ctx)
+    return out
+
+
+def target_to_theta(y, mean, std, out=None):
+    import torch
+    B = y.shape[0]
+    ctx = context(y.device.index)
+    out = torch.empty(B, 5, dtype=torch.float64, device=y.device) if out is None else out
+    _check(load().hf_target_to_theta(ctx, B, _ptr(y), _ptr(mean), _ptr(std), _ptr(out),
+                                     _stream(y.device)), ctx)
+    return out
+
+
+def mlp_forward(params, x, y=None, workspace=None):
+    import torch
+    B = x.shape[0]
+    ctx = context(x.device.index)
+    y = torch.empty(B, MLP_OUT_PAD, dtype=torch.float32, device=x.device) if y is None else y
+    ws = mlp_workspace(B, x.device) if workspace is None else workspace
+    _check(load().hf_mlp_forward(ctx, B, _ptr(params), _ptr(x), _ptr(y), _ptr(ws),
+                                 _stream(x.device)), ctx)
+    return y
+
+
+def mlp_train_step(params, adam_m, adam_v, step, lr, wd, x, target, grads, loss, workspace):
+    B = x.shape[0]
+    ctx = context(x.device.index)
+    _check(load().hf_mlp_train_step(ctx, B, _ptr(params), _ptr(adam_m), _ptr(adam_v), int(step),
+                                    float(lr), float(wd), _ptr(x), _ptr(target), _ptr(grads),
+                                    _ptr(loss), _ptr(workspace), _stream(x.device)), ctx)

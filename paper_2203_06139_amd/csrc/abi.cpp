@@ -13,6 +13,7 @@
 
 #include "../../include/histfit.h"
 #include "fit_kernels.hpp"
+#include "mlp.hpp"
 #include "nll_kernels.hpp"
 
 #define HF_EXPORT extern "C" __attribute__((visibility("default")))
@@ -22,6 +23,9 @@ static_assert(HF_NEYMAN == hf::OBJ_NEYMAN && HF_PEARSON == hf::OBJ_PEARSON &&
               "objective codes");
 static_assert(HF_U32 == hf::DT_U32 && HF_F32 == hf::DT_F32 && HF_F64 == hf::DT_F64, "dtype codes");
 static_assert(HF_ST_DOMAIN == hf::ST_DOMAIN && HF_ST_NONFINITE == hf::ST_NONFINITE, "status bits");
+static_assert(HF_MLP_IN == hf::kMlpIn && HF_MLP_HIDDEN == hf::kMlpHidden && HF_MLP_OUT == hf::kMlpOut &&
+                  HF_MLP_OUT_PAD == hf::kMlpOutPad,
+              "network shape");
 
 namespace {
 
@@ -363,4 +367,113 @@ HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
   if (e == hipErrorNotSupported) return fail(c, HF_EUNSUPPORTED, "no fit kernel for this model");
   if (e != hipSuccess) return hip_fail(c, e, "fit launch");
   return HF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned initialiser
+// ---------------------------------------------------------------------------
+namespace {
+
+int mlp_common(hf_ctx* c, int32_t B, const void* ws) {
+  if (!c) return HF_EINVAL;
+  if (B < 64 || B % 64 != 0) return fail(c, HF_EINVAL, "batch must be a positive multiple of 64");
+  if (!ws) return fail(c, HF_EINVAL, "workspace is NULL");
+  return use_device(c);
+}
+
+int batch_common(hf_ctx* c, int32_t B, const void* counts, int32_t dtype, const int64_t* offsets) {
+  if (!c) return HF_EINVAL;
+  if (B < 1) return fail(c, HF_EINVAL, "B must be >= 1");
+  if (!counts || !offsets) return fail(c, HF_EINVAL, "counts/offsets is NULL");
+  if (dtype < HF_U32 || dtype > HF_F64) return fail(c, HF_EINVAL, "counts_dtype %d unknown", dtype);
+  return use_device(c);
+}
+
+}  // namespace
+
+HF_EXPORT int64_t hf_mlp_nparams(void) { return hf::MlpLayout::kTotal; }
+
+HF_EXPORT int64_t hf_mlp_workspace_bytes(int32_t batch) {
+  if (batch < 64 || batch % 64 != 0) return HF_EINVAL;
+  return hf::mlp_workspace_bytes(batch);
+}
+
+HF_EXPORT int hf_rebin_lognorm(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
+                               const int64_t* offsets, float in_mean, float in_std, float* out,
+                               hf_stream_t stream) {
+  int rc = batch_common(c, B, counts, dtype, offsets);
+  if (rc) return rc;
+  if (!out) return fail(c, HF_EINVAL, "out is NULL");
+  if (!(in_std > 0.0f) || !std::isfinite(in_mean)) return fail(c, HF_EINVAL, "bad in_mean/in_std");
+  hipError_t e = hf::rebin_lognorm(B, counts, dtype, offsets, in_mean, in_std, out,
+                                   reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HF_OK : hip_fail(c, e, "rebin_lognorm");
+}
+
+HF_EXPORT int hf_default_starts(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
+                                const int64_t* offsets, const double* ranges, const hf_model* m,
+                                double* theta0, hf_stream_t stream) {
+  int rc = batch_common(c, B, counts, dtype, offsets);
+  if (rc) return rc;
+  rc = check_model(c, m);
+  if (rc) return rc;
+  if (m->kind != HF_GAUSS_EXP || m->n_gauss != 1)
+    return fail(c, HF_EUNSUPPORTED, "default starts exist for one Gaussian + exponential only");
+  if (!ranges || !theta0) return fail(c, HF_EINVAL, "ranges/theta0 is NULL");
+  hipError_t e = hf::default_starts(B, counts, dtype, offsets, ranges, m->t_shift, m->t_scale, theta0,
+                                    reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HF_OK : hip_fail(c, e, "default_starts");
+}
+
+HF_EXPORT int hf_column_stats(hf_ctx* c, int64_t n, int32_t cols, const float* x, float* mean,
+                              float* std_out, hf_stream_t stream) {
+  if (!c) return HF_EINVAL;
+  if (n < 1 || cols < 1 || !x || !mean || !std_out) return fail(c, HF_EINVAL, "bad arguments");
+  int rc = use_device(c);
+  if (rc) return rc;
+  hipError_t e = hf::column_stats(n, cols, x, mean, std_out, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HF_OK : hip_fail(c, e, "column_stats");
+}
+
+HF_EXPORT int hf_theta_to_target(hf_ctx* c, int32_t B, const double* theta, const float* mean,
+                                 const float* std_in, float* target, hf_stream_t stream) {
+  if (!c) return HF_EINVAL;
+  if (B < 1 || !theta || !mean || !std_in || !target) return fail(c, HF_EINVAL, "bad arguments");
+  int rc = use_device(c);
+  if (rc) return rc;
+  hipError_t e = hf::theta_to_target(B, theta, mean, std_in, target,
+                                     reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HF_OK : hip_fail(c, e, "theta_to_target");
+}
+
+HF_EXPORT int hf_target_to_theta(hf_ctx* c, int32_t B, const float* y, const float* mean,
+                                 const float* std_in, double* theta, hf_stream_t stream) {
+  if (!c) return HF_EINVAL;
+  if (B < 1 || !theta || !mean || !std_in || !y) return fail(c, HF_EINVAL, "bad arguments");
+  int rc = use_device(c);
+  if (rc) return rc;
+  hipError_t e = hf::target_to_theta(B, y, mean, std_in, theta, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HF_OK : hip_fail(c, e, "target_to_theta");
+}
+
+HF_EXPORT int hf_mlp_forward(hf_ctx* c, int32_t batch, const float* params, const float* x, float* y,
+                             void* workspace, hf_stream_t stream) {
+  int rc = mlp_common(c, batch, workspace);
+  if (rc) return rc;
+  if (!params || !x || !y) return fail(c, HF_EINVAL, "params/x/y is NULL");
+  hipError_t e = hf::mlp_forward(batch, params, x, y, workspace, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HF_OK : hip_fail(c, e, "mlp_forward");
+}
+
+HF_EXPORT int hf_mlp_train_step(hf_ctx* c, int32_t batch, float* params, float* adam_m, float* adam_v,
+                                int32_t step, float lr, float wd, const float* x, const float* target,
+                                float* grads, float* loss_out, void* workspace, hf_stream_t stream) {
+  int rc = mlp_common(c, batch, workspace);
+  if (rc) return rc;
+  if (!params || !adam_m || !adam_v || !x || !target || !grads || !loss_out)
+    return fail(c, HF_EINVAL, "a pointer argument is NULL");
+  if (step < 1 || !(lr > 0.0f) || !(wd >= 0.0f)) return fail(c, HF_EINVAL, "bad step/lr/wd");
+  hipError_t e = hf::mlp_train_step(batch, params, adam_m, adam_v, step, lr, wd, x, target, grads,
+                                    loss_out, workspace, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? HF_OK : hip_fail(c, e, "mlp_train_step");
 }

@@ -1,0 +1,420 @@
+// mlp.hip -- learned initialiser: rebinning, default starts, and the BF16
+// MFMA training / inference kernels of the 256-512-512-512-5 GELU network.
+//
+// Dense layers use v_mfma_f32_16x16x32_bf16 (gfx950): one wave computes a
+// 32x32 output tile as 2x2 MFMA tiles, each lane feeding 8 consecutive K
+// values of one A row and one B row per instruction, loaded as 16 bytes
+// straight from L2 (the operands of this network are at most a few MB).
+// Every GEMM is "NT": C[m][n] = sum_k A[m][k] B[n][k] with K contiguous in
+// both operands, so the layers also keep transposed copies of activations,
+// adjoints and weights; epilogues fuse bias, GELU, GELU' and BF16 rounding.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+#include "mlp.hpp"
+
+namespace hf {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_prime(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  if (m0 >= g.M || n0 >= g.N) return;  // whole wave; the kernel has no barriers
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  const uint16_t* a0p = g.A + static_cast<int64_t>(m0 + r) * g.lda + kq;
+  const uint16_t* a1p = a0p + 16 * g.lda;
+  const uint16_t* b0p = g.B + static_cast<int64_t>(n0 + r) * g.ldb + kq;
+  const uint16_t* b1p = b0p + 16 * g.ldb;
+  f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
+  for (int k = 0; k < g.K; k += 32) {
+    const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(a0p + k);
+    const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(a1p + k);
+    const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(b0p + k);
+    const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(b1p + k);
+    c00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, c00, 0, 0, 0);
+    c01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, c01, 0, 0, 0);
+    c10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, c10, 0, 0, 0);
+    c11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, c11, 0, 0, 0);
+  }
+  // lane holds D[4 (lane/16) + q][lane % 16] of each 16x16 tile
+  const f32x4 acc[2][2] = {{c00, c01}, {c10, c11}};
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + 16 * i + 4 * (lane >> 4) + q;
+        const int n = n0 + 16 * j + r;
+        float v = acc[i][j][q];
+        if (g.epi == EPI_BIAS_GELU || g.epi == EPI_BIAS) v += g.bias[n];
+        if (g.epi == EPI_BIAS_GELU) {
+          g.cf[static_cast<int64_t>(m) * g.ldcf + n] = v;  // pre-activation, for GELU'
+          v = gelu(v);
+        } else if (g.epi == EPI_GELU_PRIME) {
+          v *= gelu_prime(g.zin[static_cast<int64_t>(m) * g.ldz + n]);
+        } else {
+          g.cf[static_cast<int64_t>(m) * g.ldcf + n] = v;
+        }
+        if (g.cb) {
+          const uint16_t b = f2bf(v);
+          g.cb[static_cast<int64_t>(m) * g.ldcb + n] = b;
+          if (g.cbt) g.cbt[static_cast<int64_t>(n) * g.ldcbt + m] = b;
+        }
+      }
+}
+
+hipError_t gemm_nt(const GemmArgs& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_nt, dim3((g.N + 63) / 64, (g.M + 63) / 64), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers of the training step
+// ---------------------------------------------------------------------------
+// W fp32 [N][K] -> W bf16 [N][K] and its transpose [K][N].
+__global__ void k_cast_nt(const float* __restrict__ w, int N, int K, uint16_t* __restrict__ wb,
+                          uint16_t* __restrict__ wt) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(N) * K) return;
+  const int n = static_cast<int>(i / K), k = static_cast<int>(i % K);
+  const uint16_t b = f2bf(w[i]);
+  wb[i] = b;
+  if (wt) wt[static_cast<int64_t>(k) * N + n] = b;
+}
+
+hipError_t cast_nt(const float* w, int N, int K, uint16_t* wb, uint16_t* wt, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(N) * K;
+  hipLaunchKernelGGL(k_cast_nt, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, w, N,
+                     K, wb, wt);
+  return hipGetLastError();
+}
+
+// loss = sum_{m, n<5} (y - t)^2 / (5B); dZ = bf16(2 (y - t) / (5B)), zero for
+// the padding columns; written [B][32] and transposed [32][B].  One block,
+// a fixed-order reduction.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t,
+                                             int B, float* loss, uint16_t* dz, uint16_t* dzt) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const float scale = 2.0f / (5.0f * static_cast<float>(B));
+  for (int i = threadIdx.x; i < B * kMlpOutPad; i += 256) {
+    const int m = i / kMlpOutPad, n = i % kMlpOutPad;
+    float d = 0.0f;
+    if (n < kMlpOut) {
+      d = y[i] - t[m * kMlpOut + n];
+      acc += static_cast<double>(d) * d;
+    }
+    const uint16_t b = f2bf(scale * d);
+    dz[i] = b;
+    dzt[static_cast<int64_t>(n) * B + m] = b;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = static_cast<float>(red[0] / (5.0 * B));
+}
+
+hipError_t mse(const float* y, const float* t, int B, float* loss, uint16_t* dz, uint16_t* dzt,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, s, y, t, B, loss, dz, dzt);
+  return hipGetLastError();
+}
+
+// db[n] = sum_m dZ[m][n] (BF16 adjoints, FP32 sum in row order).
+__global__ void k_bias_grad(const uint16_t* __restrict__ dz, int B, int N, float* __restrict__ db) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float acc = 0.0f;
+  for (int m = 0; m < B; ++m) acc += bf2f(dz[static_cast<int64_t>(m) * N + n]);
+  db[n] = acc;
+}
+
+hipError_t bias_grad(const uint16_t* dz, int B, int N, float* db, hipStream_t s) {
+  hipLaunchKernelGGL(k_bias_grad, dim3((N + 255) / 256), dim3(256), 0, s, dz, B, N, db);
+  return hipGetLastError();
+}
+
+// AdamW with decoupled weight decay (Loshchilov & Hutter), FP32 state.
+__global__ void k_adamw(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                        const float* __restrict__ g, int64_t n, float lr, float wd, float bc1,
+                        float bc2) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / bc1, vh = vi / bc2;
+  p[i] -= lr * (mh / (sqrtf(vh) + 1e-8f) + wd * p[i]);
+}
+
+hipError_t adamw(float* p, float* m, float* v, const float* g, int64_t n, float lr, float wd,
+                 int step, hipStream_t s) {
+  const float bc1 = 1.0f - powf(0.9f, static_cast<float>(step));
+  const float bc2 = 1.0f - powf(0.999f, static_cast<float>(step));
+  hipLaunchKernelGGL(k_adamw, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, p, m,
+                     v, g, n, lr, wd, bc1, bc2);
+  return hipGetLastError();
+}
+
+// x fp32 [B][256] -> bf16 [B][256] and transposed [256][B].
+__global__ void k_cast_input(const float* __restrict__ x, int B, uint16_t* a, uint16_t* at) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * kMlpIn) return;
+  const int m = i / kMlpIn, k = i % kMlpIn;
+  const uint16_t b = f2bf(x[i]);
+  a[i] = b;
+  if (at) at[static_cast<int64_t>(k) * B + m] = b;
+}
+
+hipError_t cast_input(const float* x, int B, uint16_t* a, uint16_t* at, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_input, dim3((B * kMlpIn + 255) / 256), dim3(256), 0, s, x, B, a, at);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Histogram -> network input, default starts, target maps, column statistics
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double count_any(const void* base, int dtype, int64_t i) {
+  if (dtype == DT_U32) return static_cast<const uint32_t*>(base)[i];
+  if (dtype == DT_F32) return static_cast<const float*>(base)[i];
+  return static_cast<const double*>(base)[i];
+}
+
+// One block per histogram; coarse sums accumulate as exact FP64 sums of
+// integer-valued (or given) counts in a fixed order per coarse bin.
+__global__ __launch_bounds__(256) void k_rebin_lognorm(const void* counts, int dtype,
+                                                       const int64_t* __restrict__ offsets,
+                                                       float in_mean, float in_std,
+                                                       float* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int64_t off = offsets[b];
+  const int64_t nb = offsets[b + 1] - off;
+  const int j = threadIdx.x;  // coarse bin
+  // fine bin i goes to coarse bin floor((2i+1) 256 / (2 nb)); the fine bins
+  // of coarse bin j are i in [lo(j), lo(j+1)) with lo(j) the count of i whose
+  // (2i+1) 256 < 2 j nb, i.e. lo(j) = ceil((2 j nb - 256) / 512) clamped.
+  auto lo_of = [nb](int jj) -> int64_t {
+    const int64_t num = 2 * static_cast<int64_t>(jj) * nb - kMlpIn;
+    if (num <= 0) return 0;
+    const int64_t q = (num + 2 * kMlpIn - 1) / (2 * kMlpIn);
+    return q < nb ? q : nb;
+  };
+  const int64_t i0 = lo_of(j), i1 = (j + 1 == kMlpIn) ? nb : lo_of(j + 1);
+  double c = 0.0;
+  for (int64_t i = i0; i < i1; ++i) c += count_any(counts, dtype, off + i);
+  const double k = static_cast<double>(i1 - i0);
+  const double v = k > 0.0 ? log1p(c / k) : 0.0;
+  out[static_cast<int64_t>(b) * kMlpIn + j] = static_cast<float>((v - in_mean) / in_std);
+}
+
+hipError_t rebin_lognorm(int B, const void* counts, int dtype, const int64_t* offsets, float mean,
+                         float std, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rebin_lognorm, dim3(B), dim3(kMlpIn), 0, s, counts, dtype, offsets, mean, std,
+                     out);
+  return hipGetLastError();
+}
+
+// Default starting point for Gauss + exp(b0 + b1 t); one block per histogram.
+__global__ __launch_bounds__(256) void k_default_starts(const void* counts, int dtype,
+                                                        const int64_t* __restrict__ offsets,
+                                                        const double* __restrict__ ranges,
+                                                        double t_shift, double t_scale,
+                                                        double* __restrict__ theta0) {
+  __shared__ int64_t best_e[256];
+  __shared__ int64_t best_i[256];
+  __shared__ double edge[2];
+  __shared__ int64_t bounds[2];
+  const int b = blockIdx.x;
+  const int64_t off = offsets[b];
+  const int64_t nb = offsets[b + 1] - off;
+  const double lo = ranges[2 * b], hi = ranges[2 * b + 1];
+  const double h = (hi - lo) / static_cast<double>(nb);
+  const int64_t ne = nb / 25 > 0 ? nb / 25 : 1;  // 4% of the bins at each edge
+  // edge means (thread 0: left, thread 1: right), summed in bin order
+  if (threadIdx.x < 2) {
+    const int64_t s0 = threadIdx.x == 0 ? 0 : nb - ne;
+    double acc = 0.0;
+    for (int64_t i = s0; i < s0 + ne; ++i) acc += count_any(counts, dtype, off + i);
+    edge[threadIdx.x] = acc / static_cast<double>(ne);
+  }
+  __syncthreads();
+  const double bk0 = fmax(edge[0], 1.0), bk1 = fmax(edge[1], 1.0);
+  // background line through the edge-block centres, in counts per bin
+  const double c0 = 0.5 * static_cast<double>(ne), c1 = static_cast<double>(nb) - 0.5 * static_cast<double>(ne);
+  const int64_t W = nb / 256 > 1 ? nb / 256 : 1;
+  const double wlen = static_cast<double>(2 * W + 1);
+  // excess E_i = window sum - round(window length x background), integer
+  int64_t be = INT64_MIN, bi = 0;
+  for (int64_t i = W + threadIdx.x; i < nb - W; i += blockDim.x) {
+    double sacc = 0.0;
+    for (int64_t q = i - W; q <= i + W; ++q) sacc += count_any(counts, dtype, off + q);
+    const double bg = bk0 + (bk1 - bk0) * ((static_cast<double>(i) + 0.5 - c0) / (c1 - c0));
+    const int64_t e = static_cast<int64_t>(rint(sacc - wlen * bg));
+    if (e > be) {  // strided increasing i: keeps the lowest index of a tie
+      be = e;
+      bi = i;
+    }
+  }
+  best_e[threadIdx.x] = be;
+  best_i[threadIdx.x] = bi;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t e = INT64_MIN, idx = nb / 2;
+    for (int t = 0; t < static_cast<int>(blockDim.x); ++t)
+      if (best_e[t] > e || (best_e[t] == e && best_i[t] < idx)) {
+        e = best_e[t];
+        idx = best_i[t];
+      }
+    if (e == INT64_MIN) {  // histogram shorter than one window
+      e = 0;
+      idx = nb / 2;
+    }
+    best_e[0] = e;
+    best_i[0] = idx;
+  }
+  __syncthreads();
+  const int64_t emax = best_e[0], imax = best_i[0];
+  if (threadIdx.x < 2) {  // walk to the half-maximum on each side
+    const int dir = threadIdx.x == 0 ? -1 : 1;
+    int64_t i = imax;
+    while (true) {
+      const int64_t nxt = i + dir;
+      if (nxt < W || nxt >= nb - W) break;
+      double sacc = 0.0;
+      for (int64_t q = nxt - W; q <= nxt + W; ++q) sacc += count_any(counts, dtype, off + q);
+      const double bg = bk0 + (bk1 - bk0) * ((static_cast<double>(nxt) + 0.5 - c0) / (c1 - c0));
+      const int64_t e = static_cast<int64_t>(rint(sacc - wlen * bg));
+      if (2 * e < emax) break;
+      i = nxt;
+    }
+    bounds[threadIdx.x] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double range = hi - lo;
+    const double fwhm = static_cast<double>(bounds[1] - bounds[0] + 1) * h;
+    const double s = fmin(fmax(fwhm / 2.3548200450309493, 0.005 * range), 0.1 * range);
+    const double A = fmax(static_cast<double>(emax) / wlen, 1.0);
+    const double m = lo + (static_cast<double>(imax) + 0.5) * h;
+    const double t0 = (lo + (c0) * h - t_shift) / t_scale;
+    const double t1 = (lo + (c1) * h - t_shift) / t_scale;
+    const double b1 = log(bk1 / bk0) / (t1 - t0);
+    const double b0v = log(bk0) - b1 * t0;
+    double* th = theta0 + static_cast<int64_t>(b) * 5;
+    th[0] = A;
+    th[1] = m;
+    th[2] = s;
+    th[3] = b0v;
+    th[4] = b1;
+  }
+}
+
+hipError_t default_starts(int B, const void* counts, int dtype, const int64_t* offsets,
+                          const double* ranges, double t_shift, double t_scale, double* theta0,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_default_starts, dim3(B), dim3(256), 0, s, counts, dtype, offsets, ranges,
+                     t_shift, t_scale, theta0);
+  return hipGetLastError();
+}
+
+__global__ void k_theta_to_target(int B, const double* __restrict__ th, const float* mean,
+                                  const float* std, float* __restrict__ t) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double* p = th + static_cast<int64_t>(b) * 5;
+  const double raw[5] = {p[1], log(fabs(p[2])), log(fabs(p[0])), p[3], p[4]};
+  for (int k = 0; k < 5; ++k)
+    t[static_cast<int64_t>(b) * 5 + k] = static_cast<float>((raw[k] - mean[k]) / std[k]);
+}
+
+__global__ void k_target_to_theta(int B, const float* __restrict__ y, const float* mean,
+                                  const float* std, double* __restrict__ th) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double v[5];
+  for (int k = 0; k < 5; ++k)
+    v[k] = static_cast<double>(y[static_cast<int64_t>(b) * kMlpOutPad + k]) * std[k] + mean[k];
+  double* p = th + static_cast<int64_t>(b) * 5;
+  p[0] = exp(v[2]);
+  p[1] = v[0];
+  p[2] = exp(v[1]);
+  p[3] = v[3];
+  p[4] = v[4];
+}
+
+hipError_t theta_to_target(int B, const double* th, const float* mean, const float* std, float* t,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_theta_to_target, dim3((B + 255) / 256), dim3(256), 0, s, B, th, mean, std, t);
+  return hipGetLastError();
+}
+
+hipError_t target_to_theta(int B, const float* y, const float* mean, const float* std, double* th,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_target_to_theta, dim3((B + 255) / 256), dim3(256), 0, s, B, y, mean, std, th);
+  return hipGetLastError();
+}
+
+// One block per column: FP64 sum and sum of squares over rows in a fixed
+// (strided, then tree) order.
+__global__ __launch_bounds__(256) void k_column_stats(int64_t n, int cols, const float* __restrict__ x,
+                                                      float* mean, float* stdv) {
+  __shared__ double s1[256], s2[256];
+  const int c = blockIdx.x;
+  double a = 0.0, q = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double v = x[i * cols + c];
+    a += v;
+    q += v * v;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mu = s1[0] / static_cast<double>(n);
+    const double var = fmax(s2[0] / static_cast<double>(n) - mu * mu, 0.0);
+    mean[c] = static_cast<float>(mu);
+    stdv[c] = static_cast<float>(var > 0.0 ? sqrt(var) : 1.0);
+  }
+}
+
+hipError_t column_stats(int64_t n, int cols, const float* x, float* mean, float* stdv,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_column_stats, dim3(cols), dim3(256), 0, s, n, cols, x, mean, stdv);
+  return hipGetLastError();
+}
+
+}  // namespace hf
