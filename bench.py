@@ -114,10 +114,14 @@ def main():
     ap.add_argument("--objective", choices=["poisson", "neyman", "pearson"], default="poisson")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits"], default="large1d",
+    ap.add_argument("--train-fits", type=int, default=1_000_000,
+                    help="learned workload: plain fits the initialiser is trained on")
+    ap.add_argument("--epochs", type=int, default=8, help="learned workload: training epochs")
+    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned"],
+                    default="large1d",
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
-                         "fit_batch")
+                         "fit_batch; learned: plain vs learned-initialiser fits of that batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after timing, copy a MIB-sized device buffer 4 times (a plain "
                          "copy of known size to scale HBM counters against)")
@@ -140,6 +144,8 @@ def main():
         return bench_hist2d(args, hf, datagen, np, torch, dev)
     if args.workload == "fits":
         return bench_fits(args, hf, datagen, np, torch, dev)
+    if args.workload == "learned":
+        return bench_learned(args, hf, datagen, np, torch, dev)
     obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
 
@@ -341,7 +347,10 @@ def bench_fits(args, hf, datagen, np, torch, dev):
     t0 = torch.as_tensor(th0, device=dev)
     m = hf.Model.from_spec(c["spec"])
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
-    kw = dict(objective=hf.POISSON, precision=prec, polish_edm=1e-3 if prec == hf.FP32_BIN else 0.0)
+    from paper_2203_06139_amd.autotune import tune_fit
+    best, _ = tune_fit(counts, off, rg, m, t0, precision=prec, use_cache=False, log=log)
+    log("autotuned: %s" % best)
+    kw = dict(objective=hf.POISSON, precision=prec, polish_edm=best["polish_edm"])
     ref = hf.fit_batch(counts, off, rg, m, t0, objective=hf.POISSON, precision=hf.FP64)
     out = hf.fit_batch(counts, off, rg, m, t0, **kw)
     torch.cuda.synchronize()
@@ -359,7 +368,48 @@ def bench_fits(args, hf, datagen, np, torch, dev):
                                       total_bins=int(c["offsets"][-1]), agreeing=ok,
                                       mean_iters=float(out.iters.float().mean().item()),
                                       mean_evals=float(out.nevals.float().mean().item()),
-                                      precision=args.precision))), flush=True)
+                                      precision=args.precision, tuning=best))), flush=True)
+
+
+def bench_learned(args, hf, datagen, np, torch, dev):
+    """fits/s at |dNLL| < 1e-6 of the plain method (default starts) and of
+    the learned initialiser (with plain-start fallback) on the 4096-histogram
+    batch; the initialiser is trained first on --train-fits plain fits of
+    4096-bin histograms from the same distribution (seeds disjoint)."""
+    from paper_2203_06139_amd.learned_init import FitSet, LearnedInit, plain_fit, timed
+    li = LearnedInit(dev, seed=0, batch=1024)
+    (kept, t_data) = timed(lambda: li.build_training_set(args.train_fits, seed=10_000, log=log))
+    (hist, t_train) = timed(lambda: li.train(epochs=args.epochs, lr=1e-3, log=log))
+    c = datagen.batch_case()
+    fs = FitSet(torch.from_numpy(c["counts"].view(np.int32)).to(dev),
+                torch.as_tensor(c["offsets"], device=dev), torch.as_tensor(c["ranges"], device=dev))
+    plain_fit(fs)  # warm-up
+    li.fit(fs)
+    (_, plain), t_plain = timed(lambda: plain_fit(fs))
+    (learned, nfb), t_learned = timed(lambda: li.fit(fs))
+    both = (plain.status == 0) & (learned.status == 0)
+    agree = both & ((plain.nll - learned.nll).abs() < 1e-6)
+    n_agree = int(agree.sum().item())
+    n_plain = int((plain.status == 0).sum().item())
+    B = len(c["nbins"])
+    print(json.dumps(dict(
+        metric="fits/s at |dNLL|<1e-6: plain vs batched+learned init", value=n_agree / t_learned,
+        unit="fits/s", n_gpus=1, steps=1, warmup=1, ms_per_step=1e3 * t_learned,
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32-bin/f64-acc",
+        data="synthetic",
+        config=dict(workload="4096 1D histograms, 256..65536 bins, Gauss + exponential background, "
+                             "Poisson; plain = default starts + fit_batch, learned = 256-bin "
+                             "rebin + BF16-MFMA MLP starts + fit_batch + plain fallback",
+                    histograms=B, train_fits=args.train_fits, train_kept=kept,
+                    epochs=args.epochs, final_train_loss=hist[-1]),
+        plain=dict(fits_per_s=n_plain / t_plain, converged=n_plain, seconds=t_plain,
+                   mean_iters=float(plain.iters.float().mean().item()),
+                   mean_evals=float(plain.nevals.float().mean().item())),
+        learned=dict(fits_per_s_agreeing=n_agree / t_learned, agreeing=n_agree, seconds=t_learned,
+                     fallbacks=nfb, mean_iters=float(learned.iters.float().mean().item()),
+                     mean_evals=float(learned.nevals.float().mean().item())),
+        speedup=(n_agree / t_learned) / max(n_plain / t_plain, 1e-30),
+        training=dict(data_seconds=t_data, train_seconds=t_train))), flush=True)
 
 
 if __name__ == "__main__":

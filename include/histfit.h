@@ -200,6 +200,17 @@ int fit_batch(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t counts_
               int32_t* nevals, hf_stream_t stream);
 
 
+/* Launch shape of fit_batch on this context (the autotuner's knobs):
+ * wg_per_cu persistent workgroups per compute unit (1..16, default 2) and
+ * cache_bins: histograms of u32 counts with at most this many bins are copied
+ * once into LDS and every evaluation reads them there (0 = never; at most
+ * hf_fit_max_cache_bins(), checked by fit_batch).  Host-only calls.        */
+int hf_fit_set_tuning(hf_ctx* ctx, int32_t wg_per_cu, int32_t cache_bins);
+int hf_fit_get_tuning(const hf_ctx* ctx, int32_t* wg_per_cu, int32_t* cache_bins);
+/* Largest cache_bins the fit kernel of this model and objective can hold in
+ * LDS next to its own state (>= 0), or a negative hf_error.               */
+int hf_fit_max_cache_bins(hf_ctx* ctx, const hf_model* model, int32_t objective);
+
 /* ------------------------------------------------------------------------
  * Learned initialiser: a dense GELU network 256 -> 512 -> 512 -> 512 -> 5
  * that predicts fit starting parameters of the Gauss + exponential model
@@ -215,12 +226,16 @@ int fit_batch(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t counts_
  *   be zero (they then stay zero).  Total hf_mlp_nparams() floats.
  * Target space (per fit, 5 values): (m, ln|s|, ln A, b0, b1), standardised by
  * per-column mean and standard deviation.
- * Batch sizes must be multiples of 64.
+ * Batch sizes must be multiples of 64.  Every call returns HF_EINVAL (and
+ * launches nothing) for a batch that is not, a NULL pointer argument, or a
+ * workspace smaller than hf_mlp_workspace_bytes(batch); shapes of the other
+ * buffers cannot be checked through plain pointers and are the caller's.
  * ---------------------------------------------------------------------- */
 enum { HF_MLP_IN = 256, HF_MLP_HIDDEN = 512, HF_MLP_OUT = 5, HF_MLP_OUT_PAD = 32 };
 
 int64_t hf_mlp_nparams(void);
-/* Device scratch a forward or training step of `batch` rows needs (bytes). */
+/* Device scratch a forward or training step of `batch` rows needs (bytes);
+ * HF_EINVAL (negative) for a batch that is not a positive multiple of 64.  */
 int64_t hf_mlp_workspace_bytes(int32_t batch);
 
 /* Rebins histogram b of counts_concat (offsets as in fit_batch) to 256 coarse
@@ -263,9 +278,12 @@ int hf_target_to_theta(hf_ctx* ctx, int32_t B, const float* y, const float* mean
 
 /* Forward pass: y = network(x).  params: device f32[hf_mlp_nparams()];
  * x: device f32[batch][256]; y: device f32[batch][32] (columns 5..31 are the
- * padding outputs); workspace: device, hf_mlp_workspace_bytes(batch).      */
+ * padding outputs); workspace: device scratch of workspace_bytes >=
+ * hf_mlp_workspace_bytes(batch) bytes, 256-byte aligned, owned by the caller
+ * and not to be used by another call until this one has completed on
+ * `stream`.                                                                */
 int hf_mlp_forward(hf_ctx* ctx, int32_t batch, const float* params, const float* x, float* y,
-                   void* workspace, hf_stream_t stream);
+                   void* workspace, int64_t workspace_bytes, hf_stream_t stream);
 
 /* One AdamW step (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay
  * wd) on the mean squared error over the 5 target columns:
@@ -274,10 +292,13 @@ int hf_mlp_forward(hf_ctx* ctx, int32_t batch, const float* params, const float*
  * correction); grads: device f32[hf_mlp_nparams()] receives the gradient of
  * this step; loss_out: device f32[1].  Rounding points: x, weights,
  * activations and output/hidden adjoints are rounded to BF16 (nearest even)
- * before each product; products accumulate in FP32.                      */
+ * before each product; products accumulate in FP32.  target: device
+ * f32[batch][5]; workspace as for hf_mlp_forward.  HF_EINVAL also for
+ * step < 1, lr <= 0 or wd < 0.                                             */
 int hf_mlp_train_step(hf_ctx* ctx, int32_t batch, float* params, float* adam_m, float* adam_v,
                       int32_t step, float lr, float wd, const float* x, const float* target,
-                      float* grads, float* loss_out, void* workspace, hf_stream_t stream);
+                      float* grads, float* loss_out, void* workspace, int64_t workspace_bytes,
+                      hf_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -120,10 +120,14 @@ def load():
     L.hf_column_stats.argtypes = [vp, i64, i32, vp, vp, vp, vp]
     L.hf_theta_to_target.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.hf_target_to_theta.argtypes = [vp, i32, vp, vp, vp, vp, vp]
-    L.hf_mlp_forward.argtypes = [vp, i32, vp, vp, vp, vp, vp]
-    L.hf_mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp, vp, vp]
+    L.hf_mlp_forward.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
+    L.hf_mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp, vp, i64, vp]
+    L.hf_fit_set_tuning.argtypes = [vp, i32, i32]
+    L.hf_fit_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.hf_fit_max_cache_bins.argtypes = [vp, ctypes.POINTER(HfModel), i32]
     for fn in (L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
-               L.hf_target_to_theta, L.hf_mlp_forward, L.hf_mlp_train_step):
+               L.hf_target_to_theta, L.hf_mlp_forward, L.hf_mlp_train_step, L.hf_fit_set_tuning,
+               L.hf_fit_get_tuning, L.hf_fit_max_cache_bins):
         fn.restype = ctypes.c_int
     _lib = L
     return L
@@ -182,6 +186,29 @@ def _dev_tensor(t, dtype, device, name):
     if not t.is_contiguous():
         t = t.contiguous()
     return t
+
+
+def _need(t, name, dtype, numel, device):
+    """Raises unless t is a contiguous `dtype` tensor on `device` with at
+    least `numel` elements: the kernels index it through a plain pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device != device or t.dtype != dtype \
+            or not t.is_contiguous() or t.numel() < numel:
+        got = (tuple(t.shape), t.dtype, str(t.device)) if isinstance(t, torch.Tensor) else type(t)
+        raise ValueError(f"{name}: need a contiguous {dtype} tensor of >= {numel} elements on "
+                         f"{device}, got {got}")
+    return t
+
+
+def _check_offsets(offsets, n_counts):
+    """Host-side check that every histogram of a batch lies inside counts."""
+    import numpy as np
+    import torch
+    if isinstance(offsets, torch.Tensor) and offsets.device.type != "cpu":
+        return  # device offsets: checked by the caller that built them
+    o = np.asarray(offsets.numpy() if isinstance(offsets, torch.Tensor) else offsets, dtype=np.int64)
+    if o.ndim != 1 or o.size < 2 or o[0] != 0 or np.any(np.diff(o) < 1) or o[-1] > n_counts:
+        raise ValueError("offsets must start at 0, increase strictly and end <= counts size")
 
 
 @dataclass
@@ -323,6 +350,25 @@ def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=PO
     return out
 
 
+def fit_set_tuning(wg_per_cu: int, cache_bins: int, device=None):
+    ctx = context(device)
+    _check(load().hf_fit_set_tuning(ctx, int(wg_per_cu), int(cache_bins)), ctx)
+
+
+def fit_get_tuning(device=None):
+    ctx = context(device)
+    w, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().hf_fit_get_tuning(ctx, ctypes.byref(w), ctypes.byref(c)), ctx)
+    return w.value, c.value
+
+
+def fit_max_cache_bins(model: Model, objective=POISSON, device=None) -> int:
+    ctx = context(device)
+    rc = load().hf_fit_max_cache_bins(ctx, ctypes.byref(model.c()), objective)
+    _check(rc if rc < 0 else 0, ctx)
+    return rc
+
+
 # ---------------------------------------------------------------------------
 # Learned initialiser (see include/histfit.h for the definitions)
 # ---------------------------------------------------------------------------
@@ -344,8 +390,12 @@ def mlp_workspace(batch: int, device):
 def _batch_args(counts_concat, offsets):
     import torch
     c = counts_concat
+    if not isinstance(c, torch.Tensor) or c.device.type != "cuda" or not c.is_contiguous():
+        raise ValueError("counts_concat must be a contiguous device tensor")
+    _check_offsets(offsets, c.numel())
     off = offsets if isinstance(offsets, torch.Tensor) and offsets.device == c.device else \
         _dev_tensor(offsets, torch.int64, c.device, "offsets")
+    _need(off, "offsets", torch.int64, 2, c.device)
     return c, off, off.numel() - 1
 
 
@@ -354,6 +404,7 @@ def rebin_lognorm(counts_concat, offsets, in_mean=0.0, in_std=1.0, out=None):
     c, off, B = _batch_args(counts_concat, offsets)
     ctx = context(c.device.index)
     out = torch.empty(B, MLP_IN, dtype=torch.float32, device=c.device) if out is None else out
+    _need(out, "out", torch.float32, B * MLP_IN, c.device)
     _check(load().hf_rebin_lognorm(ctx, B, _ptr(c), _dtype_code(c), _ptr(off), float(in_mean),
                                    float(in_std), _ptr(out), _stream(c.device)), ctx)
     return out
@@ -363,8 +414,10 @@ def default_starts(counts_concat, offsets, ranges, model: Model, out=None):
     import torch
     c, off, B = _batch_args(counts_concat, offsets)
     ctx = context(c.device.index)
-    rg = _dev_tensor(ranges, torch.float64, c.device, "ranges")
+    rg = _need(_dev_tensor(ranges, torch.float64, c.device, "ranges"), "ranges", torch.float64,
+               2 * B, c.device)
     out = torch.empty(B, 5, dtype=torch.float64, device=c.device) if out is None else out
+    _need(out, "out", torch.float64, B * 5, c.device)
     _check(load().hf_default_starts(ctx, B, _ptr(c), _dtype_code(c), _ptr(off), _ptr(rg),
                                     ctypes.byref(model.c()), _ptr(out), _stream(c.device)), ctx)
     return out
@@ -386,10 +439,15 @@ def column_stats(x):
 def theta_to_target(theta, mean, std, out=None):
     import torch
     B = theta.shape[0]
-    ctx = context(theta.device.index)
-    out = torch.empty(B, 5, dtype=torch.float32, device=theta.device) if out is None else out
-    _check(load().hf_theta_to_target(ctx, B, _ptr(theta.contiguous()), _ptr(mean), _ptr(std),
-                                     _ptr(out), _stream(theta.device)), ctx)
+    dev = theta.device
+    ctx = context(dev.index)
+    theta = _need(theta.contiguous(), "theta", torch.float64, B * 5, dev)
+    _need(mean, "mean", torch.float32, 5, dev)
+    _need(std, "std", torch.float32, 5, dev)
+    out = torch.empty(B, 5, dtype=torch.float32, device=dev) if out is None else out
+    _need(out, "out", torch.float32, B * 5, dev)
+    _check(load().hf_theta_to_target(ctx, B, _ptr(theta), _ptr(mean), _ptr(std),
+                                     _ptr(out), _stream(dev)), ctx)
     return out
 
 
@@ -397,7 +455,11 @@ def target_to_theta(y, mean, std, out=None):
     import torch
     B = y.shape[0]
     ctx = context(y.device.index)
+    _need(y, "y", torch.float32, B * MLP_OUT_PAD, y.device)
+    _need(mean, "mean", torch.float32, 5, y.device)
+    _need(std, "std", torch.float32, 5, y.device)
     out = torch.empty(B, 5, dtype=torch.float64, device=y.device) if out is None else out
+    _need(out, "out", torch.float64, B * 5, y.device)
     _check(load().hf_target_to_theta(ctx, B, _ptr(y), _ptr(mean), _ptr(std), _ptr(out),
                                      _stream(y.device)), ctx)
     return out
@@ -407,16 +469,31 @@ def mlp_forward(params, x, y=None, workspace=None):
     import torch
     B = x.shape[0]
     ctx = context(x.device.index)
-    y = torch.empty(B, MLP_OUT_PAD, dtype=torch.float32, device=x.device) if y is None else y
-    ws = mlp_workspace(B, x.device) if workspace is None else workspace
-    _check(load().hf_mlp_forward(ctx, B, _ptr(params), _ptr(x), _ptr(y), _ptr(ws),
-                                 _stream(x.device)), ctx)
+    dev = x.device
+    y = torch.empty(B, MLP_OUT_PAD, dtype=torch.float32, device=dev) if y is None else y
+    ws = mlp_workspace(B, dev) if workspace is None else workspace
+    _need(params, "params", torch.float32, mlp_nparams(), dev)
+    _need(x, "x", torch.float32, B * MLP_IN, dev)
+    _need(y, "y", torch.float32, B * MLP_OUT_PAD, dev)
+    _need(ws, "workspace", torch.uint8, 1, dev)
+    _check(load().hf_mlp_forward(ctx, B, _ptr(params), _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
+                                 _stream(dev)), ctx)
     return y
 
 
 def mlp_train_step(params, adam_m, adam_v, step, lr, wd, x, target, grads, loss, workspace):
+    import torch
     B = x.shape[0]
-    ctx = context(x.device.index)
+    dev = x.device
+    ctx = context(dev.index)
+    n = mlp_nparams()
+    for t, name in ((params, "params"), (adam_m, "adam_m"), (adam_v, "adam_v"), (grads, "grads")):
+        _need(t, name, torch.float32, n, dev)
+    _need(x, "x", torch.float32, B * MLP_IN, dev)
+    _need(target, "target", torch.float32, B * MLP_OUT, dev)
+    _need(loss, "loss", torch.float32, 1, dev)
+    _need(workspace, "workspace", torch.uint8, 1, dev)
     _check(load().hf_mlp_train_step(ctx, B, _ptr(params), _ptr(adam_m), _ptr(adam_v), int(step),
                                     float(lr), float(wd), _ptr(x), _ptr(target), _ptr(grads),
-                                    _ptr(loss), _ptr(workspace), _stream(x.device)), ctx)
+                                    _ptr(loss), _ptr(workspace), workspace.numel(), _stream(dev)),
+           ctx)

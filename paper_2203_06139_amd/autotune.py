@@ -1,0 +1,97 @@
+"""Autotuner of fit_batch's launch shape.
+
+Searches persistent workgroups per CU x the LDS count cache (in bins) x the
+FP32->FP64 polish threshold by timing fit_batch (HIP events) on a sample of
+the batch to be fitted, keeps the fastest configuration whose fits agree with
+the FP64 fit of the same sample (|dNLL| < 1e-6 where both converge), applies
+it to the context, and caches it as JSON keyed by (GPU arch, CU count, model,
+objective, precision).  Cache file: $HF_AUTOTUNE_CACHE or
+~/.cache/histfit/autotune.json.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import torch
+
+from . import FP32_BIN, FP64, POISSON, Model, fit_batch, fit_max_cache_bins, fit_set_tuning
+
+WG_PER_CU = (1, 2, 4, 8)
+POLISH = (1e-2, 1e-3, 1e-4)
+
+
+def cache_path() -> str:
+    return os.environ.get("HF_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "histfit", "autotune.json"))
+
+
+def key(model: Model, objective: int, precision: int) -> str:
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return "%s/%dCU/kind%d-g%d-d%d/obj%d/prec%d" % (p.gcnArchName.split(":")[0],
+                                                  p.multi_processor_count, model.kind,
+                                                  model.n_gauss, model.poly_degree, objective,
+                                                  precision)
+
+
+def _time(fn, reps=2):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_fit(counts, offsets, ranges, model: Model, theta0, objective=POISSON, precision=FP32_BIN,
+             sample=512, seed=0, use_cache=True, log=None):
+    """Tunes on `sample` histograms drawn from the batch and applies the best
+    configuration; returns (config dict, all timings)."""
+    from .learned_init import FitSet, subset
+    k = key(model, objective, precision)
+    path = cache_path()
+    if use_cache and os.path.exists(path):
+        with open(path) as f:
+            known = json.load(f)
+        if k in known:
+            c = known[k]
+            fit_set_tuning(c["wg_per_cu"], c["cache_bins"])
+            return c, []
+    B = offsets.numel() - 1
+    g = torch.Generator().manual_seed(seed)
+    idx = torch.randperm(B, generator=g)[:min(sample, B)].sort().values
+    fs = subset(FitSet(counts, offsets.to(counts.device), ranges.to(counts.device)), idx.to(counts.device))
+    th0 = theta0.to(counts.device)[idx.to(counts.device)].contiguous()
+    ref = fit_batch(fs.counts, fs.offsets, fs.ranges, model, th0, objective=objective, precision=FP64)
+    cap = max(0, fit_max_cache_bins(model, objective))
+    caches = sorted({0, min(cap, 8192), min(cap, 16384), cap})
+    polishes = POLISH if precision == FP32_BIN else (0.0,)
+    results = []
+    for wg, cb, pol in itertools.product(WG_PER_CU, caches, polishes):
+        fit_set_tuning(wg, cb)
+        run = lambda: fit_batch(fs.counts, fs.offsets, fs.ranges, model, th0, objective=objective,
+                                precision=precision, polish_edm=pol)
+        ms = _time(run)
+        out = run()
+        both = (out.status == 0) & (ref.status == 0)
+        agree = bool(((out.nll - ref.nll).abs()[both] < 1e-6).all().item())
+        results.append(dict(wg_per_cu=wg, cache_bins=cb, polish_edm=pol, ms=ms, agree=agree))
+        if log:
+            log(results[-1])
+    ok = [r for r in results if r["agree"]] or results
+    best = min(ok, key=lambda r: r["ms"])
+    fit_set_tuning(best["wg_per_cu"], best["cache_bins"])
+    if use_cache:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        known = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                known = json.load(f)
+        known[k] = best
+        with open(path, "w") as f:
+            json.dump(known, f, indent=1)
+    return best, results

@@ -198,7 +198,7 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   rc = use_device(c);
   if (rc) return rc;
 
-  hf::LaunchFn fn = two_d ? hf::pick_2d(grad, prec == HF_FP32_BIN)
+  hf::LaunchFn fn = two_d ? hf::pick_2d(obj, grad, prec == HF_FP32_BIN)
                           : pick_1d(m->n_gauss, bkg_code(m), obj, grad, prec == HF_FP32_BIN);
   if (!fn) return fail(c, HF_EUNSUPPORTED, "no kernel for this model");
 
@@ -237,7 +237,10 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
     it = c->occupancy.emplace(fn, occ < 1 ? 1 : occ).first;
   }
   const int per_cu = c->blocks_per_cu > 0 ? c->blocks_per_cu : it->second;
-  const int grid = objective_grid(c, a.nx * a.ny, two_d ? 4 : hf::kChunk, per_cu);
+  // 2D work items are 16-bin pieces of one row (a row's tail is a short piece)
+  const int64_t items_bins =
+      two_d ? ((a.nx + hf::kChunk2D - 1) / hf::kChunk2D) * hf::kChunk2D * a.ny : a.nx;
+  const int grid = objective_grid(c, items_bins, two_d ? hf::kChunk2D : hf::kChunk, per_cu);
   hipError_t e = fn(a, grid, stream, nullptr);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return HF_OK;
@@ -336,6 +339,12 @@ HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
     return fail(c, HF_EINVAL, "precision %d unknown", prec);
   if (o->max_iter < 1 || o->ls_max < 1 || o->ls_max > 60 || !(o->edm_tol >= 0.0))
     return fail(c, HF_EINVAL, "fit options out of range");
+  if (c->fit.cache_bins > 0) {
+    const int cap = hf::fit_max_cache_bins(m->n_gauss, bkg_code(m), obj);
+    if (c->fit.cache_bins > cap)
+      return fail(c, HF_EINVAL, "LDS cache of %d bins exceeds the %d this fit kernel can hold",
+                  c->fit.cache_bins, cap);
+  }
   rc = use_device(c);
   if (rc) return rc;
 
@@ -362,6 +371,7 @@ HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
   a.t_shift = m->t_shift;
   a.t_scale = m->t_scale;
   a.P = nparams(m);
+  a.log_lut = c->log_lut;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hf::launch_fit(m->n_gauss, bkg_code(m), a, c->num_cu, &c->fit, s);
   if (e == hipErrorNotSupported) return fail(c, HF_EUNSUPPORTED, "no fit kernel for this model");
@@ -374,10 +384,16 @@ HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
 // ---------------------------------------------------------------------------
 namespace {
 
-int mlp_common(hf_ctx* c, int32_t B, const void* ws) {
+int mlp_common(hf_ctx* c, int32_t B, const void* ws, int64_t ws_bytes) {
   if (!c) return HF_EINVAL;
   if (B < 64 || B % 64 != 0) return fail(c, HF_EINVAL, "batch must be a positive multiple of 64");
   if (!ws) return fail(c, HF_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(c, HF_EINVAL, "workspace must be 256-byte aligned");
+  const int64_t need = hf::mlp_workspace_bytes(B);
+  if (ws_bytes < need)
+    return fail(c, HF_EINVAL, "workspace of %lld bytes, batch %d needs %lld",
+                static_cast<long long>(ws_bytes), B, static_cast<long long>(need));
   return use_device(c);
 }
 
@@ -457,8 +473,8 @@ HF_EXPORT int hf_target_to_theta(hf_ctx* c, int32_t B, const float* y, const flo
 }
 
 HF_EXPORT int hf_mlp_forward(hf_ctx* c, int32_t batch, const float* params, const float* x, float* y,
-                             void* workspace, hf_stream_t stream) {
-  int rc = mlp_common(c, batch, workspace);
+                             void* workspace, int64_t workspace_bytes, hf_stream_t stream) {
+  int rc = mlp_common(c, batch, workspace, workspace_bytes);
   if (rc) return rc;
   if (!params || !x || !y) return fail(c, HF_EINVAL, "params/x/y is NULL");
   hipError_t e = hf::mlp_forward(batch, params, x, y, workspace, reinterpret_cast<hipStream_t>(stream));
@@ -467,8 +483,9 @@ HF_EXPORT int hf_mlp_forward(hf_ctx* c, int32_t batch, const float* params, cons
 
 HF_EXPORT int hf_mlp_train_step(hf_ctx* c, int32_t batch, float* params, float* adam_m, float* adam_v,
                                 int32_t step, float lr, float wd, const float* x, const float* target,
-                                float* grads, float* loss_out, void* workspace, hf_stream_t stream) {
-  int rc = mlp_common(c, batch, workspace);
+                                float* grads, float* loss_out, void* workspace,
+                                int64_t workspace_bytes, hf_stream_t stream) {
+  int rc = mlp_common(c, batch, workspace, workspace_bytes);
   if (rc) return rc;
   if (!params || !adam_m || !adam_v || !x || !target || !grads || !loss_out)
     return fail(c, HF_EINVAL, "a pointer argument is NULL");
@@ -476,4 +493,31 @@ HF_EXPORT int hf_mlp_train_step(hf_ctx* c, int32_t batch, float* params, float* 
   hipError_t e = hf::mlp_train_step(batch, params, adam_m, adam_v, step, lr, wd, x, target, grads,
                                     loss_out, workspace, reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? HF_OK : hip_fail(c, e, "mlp_train_step");
+}
+
+HF_EXPORT int hf_fit_set_tuning(hf_ctx* c, int32_t wg_per_cu, int32_t cache_bins) {
+  if (!c) return HF_EINVAL;
+  if (wg_per_cu < 1 || wg_per_cu > 16) return fail(c, HF_EINVAL, "wg_per_cu outside 1..16");
+  if (cache_bins < 0) return fail(c, HF_EINVAL, "cache_bins must be >= 0");
+  c->fit.wg_per_cu = wg_per_cu;
+  c->fit.cache_bins = cache_bins;
+  return HF_OK;
+}
+
+HF_EXPORT int hf_fit_get_tuning(const hf_ctx* c, int32_t* wg_per_cu, int32_t* cache_bins) {
+  if (!c || !wg_per_cu || !cache_bins) return HF_EINVAL;
+  *wg_per_cu = c->fit.wg_per_cu;
+  *cache_bins = c->fit.cache_bins;
+  return HF_OK;
+}
+
+HF_EXPORT int hf_fit_max_cache_bins(hf_ctx* c, const hf_model* m, int32_t objective) {
+  if (!c) return HF_EINVAL;
+  int rc = check_model(c, m);
+  if (rc) return rc;
+  if (m->kind == HF_GAUSS2D) return fail(c, HF_EUNSUPPORTED, "fit_batch takes 1D models only");
+  if (objective < HF_NEYMAN || objective > HF_POISSON) return fail(c, HF_EINVAL, "objective unknown");
+  rc = use_device(c);
+  if (rc) return rc;
+  return hf::fit_max_cache_bins(m->n_gauss, bkg_code(m), objective);
 }

@@ -106,10 +106,14 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
     lk[k] = l;
     acc[0] = fma(w[k], l, acc[0]);
     if constexpr (GRAD) {
-      // ---- reverse sweep: mu_bar = w ubar (see bin_1d for the adjoint chain) ----
+      // ---- reverse sweep: mu_bar = w ubar ----
       const double mb = w[k] * ub;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
+        // G = A e:  A_bar += mb e ;  e_bar = mb A
+        // e = exp(q): q_bar = e_bar e = mb G ; q = -z^2/2: z_bar = -q_bar z
+        // z = (x - m)/s: m_bar = -z_bar/s ; s_bar = -z_bar z / s  (1/s applied
+        // once to the totals, see Model1D::final_factor)
         acc[1 + 3 * g] = fma(mb, ek[g], acc[1 + 3 * g]);
         const double zb = mb * G[g] * z[g];
         acc[2 + 3 * g] += zb;
@@ -117,6 +121,7 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
       }
       constexpr int k0 = 1 + 3 * NG;
       if constexpr (BKG == BKG_EXP) {
+        // E = exp(b0 + b1 t): b0_bar += mb E ; b1_bar += mb E t
         const double eb = mb * E;
         acc[k0] += eb;
         acc[k0 + 1] = fma(eb, t, acc[k0 + 1]);

@@ -37,110 +37,6 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 
 // --------------------------------------------------------------------------
-// FP32 hardware transcendentals used by the FP32-per-bin variant.  On gfx950
-// FP64 FMA issues at the same rate as non-packed FP32, so that variant keeps
-// ordinary arithmetic in FP64 and narrows only the steps that have cheap
-// FP32 instructions: exp2, log2 and the reciprocal.
-// --------------------------------------------------------------------------
-__device__ __forceinline__ double exp_f32hw(double q) {
-  // e^q = 2^(q log2 e); the exponent is rounded to FP32 once.
-  const float y = static_cast<float>(q * 1.4426950408889634);
-  return static_cast<double>(__builtin_amdgcn_exp2f(y));
-}
-
-__device__ __forceinline__ double rcp_f32hw(double d) {
-  // FP32 reciprocal seed refined by one FP64 Newton step (~1e-14 relative).
-  const double r0 = static_cast<double>(__builtin_amdgcn_rcpf(static_cast<float>(d)));
-  return r0 * fma(-d, r0, 2.0);
-}
-
-__device__ __forceinline__ double log_f32hw(double x) {
-  return 0.6931471805599453 * static_cast<double>(__builtin_amdgcn_logf(static_cast<float>(x)));
-}
-
-// r - log(1 + r) for r > -1 without cancellation: with u = r/(2+r),
-// log(1+r) = 2 atanh(u) = 2(u + u^3/3 + u^5/5 + ...) and r - 2u = r u, so
-// r - log1p(r) = r u - 2 u^3 (1/3 + u^2/5 + u^4/7 + ...).  The series is
-// used for |u| < 1/3 (-0.5 < r < 1), the direct form elsewhere.
-__device__ __forceinline__ double rmlog1p_f32hw(double r) {
-  const double u = r * rcp_f32hw(2.0 + r);
-  if (fabs(u) < (1.0 / 3.0)) {
-    const double v = u * u;
-    double p = 1.0 / 15.0;
-    p = fma(p, v, 1.0 / 13.0);
-    p = fma(p, v, 1.0 / 11.0);
-    p = fma(p, v, 1.0 / 9.0);
-    p = fma(p, v, 1.0 / 7.0);
-    p = fma(p, v, 1.0 / 5.0);
-    p = fma(p, v, 1.0 / 3.0);
-    return fma(r, u, -2.0 * u * v * p);
-  }
-  return r - log_f32hw(1.0 + r);
-}
-
-// --------------------------------------------------------------------------
-// Objective term l(n, mu) and its adjoint seed ubar = dl/dmu.
-// Returns 0 for a regular term, 1 for a domain error (l = +inf, ubar = 0),
-// 2 for a skipped bin (l = 0, ubar = 0).
-// --------------------------------------------------------------------------
-template <bool F32BIN>
-__device__ __forceinline__ int objective(int obj, double n, double mu, double& l, double& ub) {
-  if (obj == OBJ_NEYMAN) {
-    if (!(n > 0.0)) {
-      l = 0.0;
-      ub = 0.0;
-      return 2;
-    }
-    const double inv = F32BIN ? rcp_f32hw(n) : 1.0 / n;
-    const double d = mu - n;
-    l = d * d * inv;
-    ub = 2.0 * d * inv;
-    return 0;
-  }
-  if (obj == OBJ_PEARSON) {
-    if (!(mu > 0.0)) {
-      l = __builtin_inf();
-      ub = 0.0;
-      return 1;
-    }
-    const double inv = F32BIN ? rcp_f32hw(mu) : 1.0 / mu;
-    const double d = n - mu;
-    const double r = n * inv;
-    l = d * d * inv;
-    ub = fma(-r, r, 1.0);
-    return 0;
-  }
-  // Poisson, saturated form
-  if (n > 0.0) {
-    if (!(mu > 0.0)) {
-      l = __builtin_inf();
-      ub = 0.0;
-      return 1;
-    }
-    if (F32BIN) {
-      // l = n (r - log1p r) with r = (mu - n)/n; ubar = (mu - n)/mu
-      const double d = mu - n;
-      l = n * rmlog1p_f32hw(d * rcp_f32hw(n));
-      ub = d * rcp_f32hw(mu);
-    } else {
-      const double inv = 1.0 / mu;
-      const double r = n * inv;
-      l = mu - n + n * log(r);
-      ub = 1.0 - r;
-    }
-    return 0;
-  }
-  if (mu < 0.0) {
-    l = __builtin_inf();
-    ub = 0.0;
-    return 1;
-  }
-  l = mu;
-  ub = 1.0;
-  return 0;
-}
-
-// --------------------------------------------------------------------------
 // 1D models.  Uniform constants derived once per thread from theta.
 // --------------------------------------------------------------------------
 template <int NG, int BKG>
@@ -197,75 +93,12 @@ struct Model1D {
   }
 };
 
-// One bin of a 1D model: forward sweep, objective, reverse sweep.
-// acc[0] accumulates w l; acc[1..P] the parameter adjoints (see final_factor).
-template <int NG, int BKG, bool GRAD, bool F32BIN, int NV>
-__device__ __forceinline__ double bin_1d(const Model1D<NG, BKG>& M, int obj, double x, double n,
-                                         double w, double (&acc)[NV], int& flags) {
-  using S = Shape1D<NG, BKG>;
-  // ---- forward sweep ----
-  double z[NG > 0 ? NG : 1], e[NG > 0 ? NG : 1], G[NG > 0 ? NG : 1];
-  double mu = 0.0;
-#pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    z[g] = (x - M.m[g]) * M.is[g];
-    const double q = -0.5 * z[g] * z[g];
-    e[g] = F32BIN ? exp_f32hw(q) : exp(q);
-    G[g] = M.A[g] * e[g];
-    mu += G[g];
-  }
-  const double t = (x - M.tshift) * M.ta;
-  double E = 0.0;
-  if constexpr (BKG == BKG_EXP) {
-    const double a = fma(M.c[1], t, M.c[0]);
-    E = F32BIN ? exp_f32hw(a) : exp(a);
-    mu += E;
-  } else if constexpr (S::NB > 0) {
-    double b = M.c[S::NB - 1];
-#pragma unroll
-    for (int j = S::NB - 2; j >= 0; --j) b = fma(b, t, M.c[j]);
-    mu += b;
-  }
-  double l, ub;
-  const int rc = objective<F32BIN>(obj, n, mu, l, ub);
-  flags |= (rc == 1) ? ST_DOMAIN : 0;
-  acc[0] = fma(w, l, acc[0]);
-  if constexpr (GRAD) {
-    // ---- reverse sweep: mu_bar = w * ubar ----
-    const double mb = w * ub;
-#pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      // G = A e:  A_bar += mb e ;  e_bar = mb A
-      // e = exp(q): q_bar = e_bar e = mb G ; q = -z^2/2: z_bar = -q_bar z
-      // z = (x - m)/s: m_bar = -z_bar/s ; s_bar = -z_bar z / s  (1/s deferred)
-      acc[1 + 3 * g] = fma(mb, e[g], acc[1 + 3 * g]);
-      const double zb = mb * G[g] * z[g];  // = -z_bar
-      acc[2 + 3 * g] += zb;
-      acc[3 + 3 * g] = fma(zb, z[g], acc[3 + 3 * g]);
-    }
-    constexpr int k0 = 1 + 3 * NG;
-    if constexpr (BKG == BKG_EXP) {
-      // E = exp(b0 + b1 t): b0_bar += mb E ; b1_bar += mb E t
-      const double eb = mb * E;
-      acc[k0] += eb;
-      acc[k0 + 1] = fma(eb, t, acc[k0 + 1]);
-    } else if constexpr (S::NB > 0) {
-      double tj = mb;
-#pragma unroll
-      for (int j = 0; j < S::NB; ++j) {
-        acc[k0 + j] += tj;
-        tj *= t;
-      }
-    }
-  }
-  return l;
-}
-
 // --------------------------------------------------------------------------
 // 2D correlated Gaussian + constant.
 // --------------------------------------------------------------------------
 struct Model2D {
   double A, mx, my, isx, isy, rho, c, invD;
+  double Dw = 0.0;  // exp(-dw^2) of the row recurrence, set by the kernel
   __device__ __forceinline__ void init(const double* __restrict__ th) {
     A = th[0];
     mx = th[1];
@@ -292,38 +125,6 @@ struct Model2D {
     }
   }
 };
-
-template <bool GRAD, bool F32BIN, int NV>
-__device__ __forceinline__ double bin_2d(const Model2D& M, int obj, double u, double v, double n,
-                                         double w, double (&acc)[NV], int& flags) {
-  // ---- forward sweep ----
-  const double uv = u * v;
-  const double Q = (fma(u, u, v * v) - 2.0 * M.rho * uv) * M.invD;
-  const double e = F32BIN ? exp_f32hw(-0.5 * Q) : exp(-0.5 * Q);
-  const double G = M.A * e;
-  const double mu = G + M.c;
-  double l, ub;
-  const int rc = objective<F32BIN>(obj, n, mu, l, ub);
-  flags |= (rc == 1) ? ST_DOMAIN : 0;
-  acc[0] = fma(w, l, acc[0]);
-  if constexpr (GRAD) {
-    // ---- reverse sweep: mu_bar = w ubar ----
-    const double mb = w * ub;
-    acc[1] = fma(mb, e, acc[1]);  // A
-    // Q_bar = -mu_bar G / 2;  dQ/du = 2(u - rho v)/D, dQ/dv = 2(v - rho u)/D,
-    // dQ/drho = 2(rho Q - u v)/D; u = (x-mx)/sx, v = (y-my)/sy.
-    const double gb = mb * G;  // = -2 Q_bar
-    const double au = gb * fma(-M.rho, v, u);
-    const double av = gb * fma(-M.rho, u, v);
-    acc[2] += au;                               // mx  (x invD/sx)
-    acc[3] += av;                               // my  (x invD/sy)
-    acc[4] = fma(au, u, acc[4]);                // sx  (x invD/sx)
-    acc[5] = fma(av, v, acc[5]);                // sy  (x invD/sy)
-    acc[6] = fma(gb, fma(-M.rho, Q, uv), acc[6]);  // rho (x invD)
-    acc[7] += mb;                               // c
-  }
-  return l;
-}
 
 // --------------------------------------------------------------------------
 // Deterministic reductions.

@@ -31,18 +31,18 @@ __global__ __launch_bounds__(kBlock) void k_rank_sizes(const int64_t* __restrict
   if (b < B) order[rank] = b;
 }
 
-FitLaunchFn pick_fit(int ng, int bkg) {
+FitLaunchFn pick_fit(int ng, int bkg, int obj) {
   switch (ng) {
     case 0:
-      return pick_fit_ng0(bkg);
+      return pick_fit_ng0(bkg, obj);
     case 1:
-      return pick_fit_ng1(bkg);
+      return pick_fit_ng1(bkg, obj);
     case 2:
-      return pick_fit_ng2(bkg);
+      return pick_fit_ng2(bkg, obj);
     case 3:
-      return pick_fit_ng3(bkg);
+      return pick_fit_ng3(bkg, obj);
     case 4:
-      return pick_fit_ng4(bkg);
+      return pick_fit_ng4(bkg, obj);
     default:
       return nullptr;
   }
@@ -53,10 +53,7 @@ FitLaunchFn pick_fit(int ng, int bkg) {
 hipError_t fit_scratch_init(FitScratch* s) {
   hipError_t e = hipMalloc(&s->counters, 256);
   if (e != hipSuccess) return e;
-  if (const char* v = std::getenv("HF_FIT_WG_PER_CU")) {
-    const int k = std::atoi(v);
-    if (k >= 1 && k <= 16) s->wg_per_cu = k;
-  }
+
   return hipMemset(s->counters, 0, 256);
 }
 
@@ -68,9 +65,17 @@ void fit_scratch_free(FitScratch* s) {
   s->cap = 0;
 }
 
+int fit_max_cache_bins(int n_gauss, int bkg, int obj) {
+  FitLaunchFn fn = pick_fit(n_gauss, bkg, obj);
+  int m = 0;
+  if (!fn || fn(FitArgs{}, 0, nullptr, &m) != hipSuccess) return 0;
+  return m > 0 ? m : 0;
+}
+
 hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s, hipStream_t st) {
-  FitLaunchFn fn = pick_fit(n_gauss, bkg);
+  FitLaunchFn fn = pick_fit(n_gauss, bkg, a.obj);
   if (!fn) return hipErrorNotSupported;
+  a.cache_bins = s->cache_bins;
   a.sorted = a.B <= kMaxRankB ? 1 : 0;
   if (a.sorted && a.B > s->cap) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -98,7 +103,7 @@ hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s
   }
   int grid = num_cu * s->wg_per_cu;
   if (grid > a.B) grid = a.B;
-  return fn(a, grid, st);
+  return fn(a, grid, st, nullptr);
 }
 
 }  // namespace hf

@@ -15,7 +15,7 @@
 // re-evaluated with FP64 bins.
 //
 // Work split: the whole workgroup evaluates the objective and gradient over
-// the histogram's bins (bin_1d + block_sum); the O(P^2) BFGS algebra is
+// the histogram's bins (chunk_1d + block_sum); the O(P^2) BFGS algebra is
 // spread over the first P or P^2 threads; scalar decisions are computed
 // redundantly by every thread from the same LDS values, so control flow
 // stays uniform without extra barriers.
@@ -24,6 +24,7 @@
 #include <float.h>
 #include <stdlib.h>
 
+#include "chunk.hpp"
 #include "device.hpp"
 #include "fit_kernels.hpp"
 
@@ -54,43 +55,68 @@ struct FitShared {
   int h;
 };
 
-// Objective and scaled-coordinate gradient of one histogram at sm.th,
-// evaluated by the whole workgroup.  Leaves f in sm.tot[0] and
-// dL/dtheta_k in sm.tot[1 + k].
-template <int NG, int BKG, bool F32BIN>
-__device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG>& sm, int64_t off, int64_t nb,
-                        double x0, double hx) {
+// Bins per thread per step of the fit's objective sweep.
+constexpr int kFitChunk = 4;
+
+// Where a histogram's counts are read from: the workgroup's LDS cache (u32)
+// or global memory (any dtype).
+struct CountsSrc {
+  const uint32_t* lds;  // non-null when cached
+  const void* glb;
+  int dtype;
+  int64_t off;
+  __device__ __forceinline__ double at(int64_t i) const {
+    return lds ? static_cast<double>(lds[i]) : count_at(glb, dtype, off + i);
+  }
+};
+
+// Objective and gradient of one histogram at sm.th, evaluated by the whole
+// workgroup with the chunked sweep (chunk_1d).  Leaves f in sm.tot[0]
+// (+inf on a domain error) and dL/dtheta_k in sm.tot[1 + k].
+template <int NG, int BKG, int OBJ, bool F32BIN>
+__device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG>& sm, const double2* lut,
+                        const CountsSrc& src, int64_t nb, double x0, double hx) {
   constexpr int NV = FitShared<NG, BKG>::NV;
+  constexpr int K = kFitChunk;
   Model1D<NG, BKG> M;
   M.init(sm.th, a.t_shift, a.t_scale);
+  M.init_grid(hx, K);
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
-  const int obj = a.obj;
-  int64_t i = threadIdx.x;
-  for (; i + 3 * kBlock < nb; i += 4 * kBlock) {
-    double n[4];
+  const int64_t nch = nb / K;
+  const double w[K] = {1.0, 1.0, 1.0, 1.0};
+  for (int64_t c = threadIdx.x; c < nch; c += kBlock) {
+    const int64_t i0 = c * K;
+    double n[K];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) n[k] = count_at(a.counts, a.dtype, off + i + k * kBlock);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      bin_1d<NG, BKG, true, F32BIN>(M, obj, fma(static_cast<double>(i + k * kBlock), hx, x0), n[k],
-                                    1.0, acc, flags);
+    for (int k = 0; k < K; ++k) n[k] = src.at(i0 + k);
+    double l[K];
+    const double xs = fma(static_cast<double>(i0), hx, x0);
+    if (M.recur)
+      chunk_1d<NG, BKG, OBJ, true, F32BIN, true>(M, lut, xs, n, w, acc, flags, l);
+    else
+      chunk_1d<NG, BKG, OBJ, true, F32BIN, false>(M, lut, xs, n, w, acc, flags, l);
   }
-  for (; i < nb; i += kBlock)
-    bin_1d<NG, BKG, true, F32BIN>(M, obj, fma(static_cast<double>(i), hx, x0),
-                                  count_at(a.counts, a.dtype, off + i), 1.0, acc, flags);
+  for (int64_t i = nch * K + threadIdx.x; i < nb; i += kBlock) {
+    const double n1[1] = {src.at(i)};
+    const double w1[1] = {1.0};
+    double l1[1];
+    chunk_1d<NG, BKG, OBJ, true, F32BIN, false>(M, lut, fma(static_cast<double>(i), hx, x0), n1, w1,
+                                                acc, flags, l1);
+  }
   block_sum<NV>(acc, flags, sm.tot, &sm.totf, sm.red, sm.redf);
   if (threadIdx.x >= 1 && threadIdx.x < NV) sm.tot[threadIdx.x] *= M.final_factor(threadIdx.x);
+  if (threadIdx.x == 0 && (sm.totf & ST_DOMAIN)) sm.tot[0] = __builtin_inf();
   __syncthreads();
 }
 
 // f(u) and g_u = sigma * dL/dtheta at theta = theta0 + sigma * u.
-template <int NG, int BKG>
-__device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG>& sm, const double* uu,
-                               double* gout, bool f32, int64_t off, int64_t nb, double x0,
-                               double hx) {
+template <int NG, int BKG, int OBJ>
+__device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG>& sm, const double2* lut,
+                               const CountsSrc& src, const double* uu, double* gout, bool f32,
+                               int64_t nb, double x0, double hx) {
   constexpr int P = FitShared<NG, BKG>::P;
   const int tid = threadIdx.x;
   if (tid < P) sm.th[tid] = sm.th0[tid];
@@ -101,9 +127,9 @@ __device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG>& sm, const d
   }
   __syncthreads();
   if (f32)
-    wg_eval<NG, BKG, true>(a, sm, off, nb, x0, hx);
+    wg_eval<NG, BKG, OBJ, true>(a, sm, lut, src, nb, x0, hx);
   else
-    wg_eval<NG, BKG, false>(a, sm, off, nb, x0, hx);
+    wg_eval<NG, BKG, OBJ, false>(a, sm, lut, src, nb, x0, hx);
   if (tid < sm.nf) {
     const int k = sm.fidx[tid];
     gout[tid] = sm.sig[k] * sm.tot[1 + k];
@@ -113,8 +139,9 @@ __device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG>& sm, const d
   return f;
 }
 
-template <int NG, int BKG>
-__device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, int b) {
+template <int NG, int BKG, int OBJ>
+__device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2* lut,
+                        uint32_t* cache, int b) {
   constexpr int P = FitShared<NG, BKG>::P;
   constexpr int NB = Shape1D<NG, BKG>::NB;
   const int tid = threadIdx.x;
@@ -134,6 +161,12 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, int b) {
   }
   const double hx = (hi - lo) / static_cast<double>(nb);
   const double x0 = lo + 0.5 * hx;
+  CountsSrc src{nullptr, a.counts, a.dtype, off};
+  if (a.dtype == DT_U32 && nb <= a.cache_bins) {  // keep the counts in LDS for all evaluations
+    const uint32_t* g = static_cast<const uint32_t*>(a.counts) + off;
+    for (int64_t i = tid; i < nb; i += kBlock) cache[i] = g[i];
+    src.lds = cache;
+  }
 
   if (tid < P) sm.th0[tid] = a.theta0[static_cast<int64_t>(b) * P + tid];
   __syncthreads();
@@ -157,7 +190,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, int b) {
   const int nf = sm.nf;
 
   bool f32 = a.f32 != 0;
-  double f = wg_objective<NG, BKG>(a, sm, sm.u, sm.g, f32, off, nb, x0, hx);
+  double f = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.u, sm.g, f32, nb, x0, hx);
   int nev = 1, it = 0, status = FIT_MAXITER;
   bool first = true;
   if (!__builtin_isfinite(f)) {
@@ -178,7 +211,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, int b) {
       if (f32 && a.polish_edm > 0.0 && edm < a.polish_edm) {
         // switch to FP64 bins for the rest of the fit
         f32 = false;
-        f = wg_objective<NG, BKG>(a, sm, sm.u, sm.g, false, off, nb, x0, hx);
+        f = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.u, sm.g, false, nb, x0, hx);
         ++nev;
         if (!__builtin_isfinite(f)) {
           status = (f == __builtin_inf()) ? FIT_DOMAIN : FIT_NONFINITE;
@@ -206,7 +239,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, int b) {
       for (int ls = 0; ls < a.ls_max; ++ls) {
         if (tid < nf) sm.un[tid] = sm.u[tid] + alpha * sm.pv[tid];
         __syncthreads();
-        fn = wg_objective<NG, BKG>(a, sm, sm.un, sm.gn, f32, off, nb, x0, hx);
+        fn = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.un, sm.gn, f32, nb, x0, hx);
         ++nev;
         if (__builtin_isfinite(fn) && fn <= f + 1e-4 * alpha * slope) {
           accepted = true;
@@ -261,7 +294,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, int b) {
     }
   }
   double nll = f;
-  if (f32 && __builtin_isfinite(f)) nll = wg_objective<NG, BKG>(a, sm, sm.u, sm.gn, false, off, nb, x0, hx);
+  if (f32 && __builtin_isfinite(f)) nll = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.u, sm.gn, false, nb, x0, hx);
   // final parameters, canonicalised
   if (tid < P) sm.th[tid] = sm.th0[tid];
   __syncthreads();
@@ -289,17 +322,20 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, int b) {
   __syncthreads();
 }
 
-template <int NG, int BKG>
+template <int NG, int BKG, int OBJ>
 __global__ __launch_bounds__(kBlock) void k_fit(FitArgs a) {
   __shared__ FitShared<NG, BKG> sm;
+  __shared__ double2 lut[OBJ == OBJ_POISSON ? kLogLut : 1];
+  extern __shared__ uint32_t cache[];  // a.cache_bins entries
   const int tid = threadIdx.x;
+  if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
   for (;;) {
     if (tid == 0) sm.h = static_cast<int>(atomicAdd(&a.counters[0], 1u));
     __syncthreads();
     const int h = sm.h;
     __syncthreads();
     if (h >= a.B) break;
-    fit_one<NG, BKG>(a, sm, a.sorted ? a.order[h] : h);
+    fit_one<NG, BKG, OBJ>(a, sm, lut, cache, a.sorted ? a.order[h] : h);
   }
   // the last workgroup to leave re-arms the queue for the next launch
   if (tid == 0) {
@@ -312,39 +348,66 @@ __global__ __launch_bounds__(kBlock) void k_fit(FitArgs a) {
   }
 }
 
-template <int NG, int BKG>
-hipError_t launch_fit_kernel(const FitArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_fit<NG, BKG>), dim3(grid), dim3(kBlock), 0, s, a);
+template <int NG, int BKG, int OBJ>
+hipError_t launch_fit_kernel(const FitArgs& a, int grid, hipStream_t s, int* max_cache) {
+  if (grid <= 0) {  // report the largest dynamic LDS cache that still fits
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k_fit<NG, BKG, OBJ>));
+    if (e != hipSuccess) return e;
+    int dev = 0, lds = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    *max_cache = static_cast<int>((lds - static_cast<int>(attr.sharedSizeBytes)) / 4);
+    return hipSuccess;
+  }
+  hipLaunchKernelGGL((k_fit<NG, BKG, OBJ>), dim3(grid), dim3(kBlock),
+                     sizeof(uint32_t) * static_cast<size_t>(a.cache_bins), s, a);
   return hipGetLastError();
 }
 
-using FitLaunchFn = hipError_t (*)(const FitArgs&, int, hipStream_t);
+using FitLaunchFn = hipError_t (*)(const FitArgs&, int, hipStream_t, int*);
 
-template <int NG>
-FitLaunchFn pick_fit_ng(int bkg) {
-  switch (bkg) {
-    case BKG_NONE:
-      if constexpr (NG == 0) return nullptr;
-      else return &launch_fit_kernel<NG, BKG_NONE>;
-    case 0:
-      return &launch_fit_kernel<NG, 0>;
-    case 1:
-      return &launch_fit_kernel<NG, 1>;
-    case 2:
-      return &launch_fit_kernel<NG, 2>;
-    case 3:
-      return &launch_fit_kernel<NG, 3>;
-    case BKG_EXP:
-      return &launch_fit_kernel<NG, BKG_EXP>;
+template <int NG, int BKG>
+FitLaunchFn pick_fit_obj(int obj) {
+  switch (obj) {
+    case OBJ_NEYMAN:
+      return &launch_fit_kernel<NG, BKG, OBJ_NEYMAN>;
+    case OBJ_PEARSON:
+      return &launch_fit_kernel<NG, BKG, OBJ_PEARSON>;
+    case OBJ_POISSON:
+      return &launch_fit_kernel<NG, BKG, OBJ_POISSON>;
     default:
       return nullptr;
   }
 }
 
-FitLaunchFn pick_fit_ng0(int bkg);
-FitLaunchFn pick_fit_ng1(int bkg);
-FitLaunchFn pick_fit_ng2(int bkg);
-FitLaunchFn pick_fit_ng3(int bkg);
-FitLaunchFn pick_fit_ng4(int bkg);
+template <int NG>
+FitLaunchFn pick_fit_ng(int bkg, int obj) {
+  switch (bkg) {
+    case BKG_NONE:
+      if constexpr (NG == 0) return nullptr;
+      else return pick_fit_obj<NG, BKG_NONE>(obj);
+    case 0:
+      return pick_fit_obj<NG, 0>(obj);
+    case 1:
+      return pick_fit_obj<NG, 1>(obj);
+    case 2:
+      return pick_fit_obj<NG, 2>(obj);
+    case 3:
+      return pick_fit_obj<NG, 3>(obj);
+    case BKG_EXP:
+      return pick_fit_obj<NG, BKG_EXP>(obj);
+    default:
+      return nullptr;
+  }
+}
+
+FitLaunchFn pick_fit_ng0(int bkg, int obj);
+FitLaunchFn pick_fit_ng1(int bkg, int obj);
+FitLaunchFn pick_fit_ng2(int bkg, int obj);
+FitLaunchFn pick_fit_ng3(int bkg, int obj);
+FitLaunchFn pick_fit_ng4(int bkg, int obj);
 
 }  // namespace hf

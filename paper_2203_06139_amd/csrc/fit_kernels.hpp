@@ -38,6 +38,8 @@ struct FitArgs {
   int32_t sorted;
   int32_t* order;     // device i32[B]: queue position -> histogram index
   unsigned* counters; // [0] queue head, [1] finished workgroups
+  const double2* log_lut;  // kLogLut entries (Poisson)
+  int32_t cache_bins;      // LDS cache capacity (u32 counts); 0 = no cache
 };
 
 // Device scratch of the fitter, owned by the context.  `order` grows with B;
@@ -46,7 +48,8 @@ struct FitScratch {
   int32_t* order = nullptr;
   int64_t cap = 0;
   unsigned* counters = nullptr;
-  int wg_per_cu = 2;
+  int wg_per_cu = 2;   // persistent workgroups per CU
+  int cache_bins = 0;  // histograms with at most this many u32 bins live in LDS
 };
 
 hipError_t fit_scratch_init(FitScratch* s);
@@ -54,5 +57,9 @@ void fit_scratch_free(FitScratch* s);
 
 // Returns hipErrorNotSupported for a model without a fit kernel.
 hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s, hipStream_t st);
+
+// Largest LDS cache (in u32 bins) a fit workgroup can hold for this model
+// and objective next to its own state.
+int fit_max_cache_bins(int n_gauss, int bkg, int obj);
 
 }  // namespace hf

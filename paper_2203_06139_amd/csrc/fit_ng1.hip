@@ -2,5 +2,5 @@
 #include "fit_impl.hpp"
 
 namespace hf {
-FitLaunchFn pick_fit_ng1(int bkg) { return pick_fit_ng<1>(bkg); }
+FitLaunchFn pick_fit_ng1(int bkg, int obj) { return pick_fit_ng<1>(bkg, obj); }
 }  // namespace hf

@@ -2,5 +2,5 @@
 #include "fit_impl.hpp"
 
 namespace hf {
-FitLaunchFn pick_fit_ng3(int bkg) { return pick_fit_ng<3>(bkg); }
+FitLaunchFn pick_fit_ng3(int bkg, int obj) { return pick_fit_ng<3>(bkg, obj); }
 }  // namespace hf

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         float v = acc[i][j][q];
         if (g.epi == EPI_BIAS_GELU || g.epi == EPI_BIAS) v += g.bias[n];
         if (g.epi == EPI_BIAS_GELU) {
-          g.cf[static_cast<int64_t>(m) * g.ldcf + n] = v;  // pre-activation, for GELU'
+          if (g.cf) g.cf[static_cast<int64_t>(m) * g.ldcf + n] = v;  // pre-activation, for GELU'
           v = gelu(v);
         } else if (g.epi == EPI_GELU_PRIME) {
           v *= gelu_prime(g.zin[static_cast<int64_t>(m) * g.ldz + n]);
@@ -85,7 +85,20 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
       }
 }
 
+// Rejects what the kernel cannot index safely: shapes off the 32 grid, row
+// strides that break the 16-byte operand loads, and a missing output or
+// epilogue operand.
 hipError_t gemm_nt(const GemmArgs& g, hipStream_t s) {
+  if (g.M < 32 || g.N < 32 || g.K < 32 || g.M % 32 || g.N % 32 || g.K % 32) return hipErrorInvalidValue;
+  if (!g.A || !g.B || g.lda < g.K || g.ldb < g.K || g.lda % 8 || g.ldb % 8) return hipErrorInvalidValue;
+  const bool bias = g.epi == EPI_BIAS || g.epi == EPI_BIAS_GELU;
+  if (bias && !g.bias) return hipErrorInvalidValue;
+  if ((g.epi == EPI_PLAIN || g.epi == EPI_BIAS) && (!g.cf || g.ldcf < g.N)) return hipErrorInvalidValue;
+  if (g.epi == EPI_BIAS_GELU && g.cf && g.ldcf < g.N) return hipErrorInvalidValue;
+  if (g.epi == EPI_GELU_PRIME && (!g.zin || g.ldz < g.N || !g.cb)) return hipErrorInvalidValue;
+  if (g.epi == EPI_BIAS_GELU && !g.cb) return hipErrorInvalidValue;
+  if ((g.cb && g.ldcb < g.N) || (g.cbt && g.ldcbt < g.M)) return hipErrorInvalidValue;
+  if (g.epi < EPI_PLAIN || g.epi > EPI_GELU_PRIME) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gemm_nt, dim3((g.N + 63) / 64, (g.M + 63) / 64), dim3(256), 0, s, g);
   return hipGetLastError();
 }
@@ -254,6 +267,10 @@ __global__ __launch_bounds__(256) void k_default_starts(const void* counts, int 
   const int b = blockIdx.x;
   const int64_t off = offsets[b];
   const int64_t nb = offsets[b + 1] - off;
+  if (nb < 1) {  // empty histogram: no start (uniform over the block)
+    if (threadIdx.x < 5) theta0[static_cast<int64_t>(b) * 5 + threadIdx.x] = __builtin_nan("");
+    return;
+  }
   const double lo = ranges[2 * b], hi = ranges[2 * b + 1];
   const double h = (hi - lo) / static_cast<double>(nb);
   const int64_t ne = nb / 25 > 0 ? nb / 25 : 1;  // 4% of the bins at each edge

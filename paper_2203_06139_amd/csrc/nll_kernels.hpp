@@ -306,6 +306,7 @@ LaunchFn pick_1d_ng1(int bkg, int obj, bool grad, bool f32);
 LaunchFn pick_1d_ng2(int bkg, int obj, bool grad, bool f32);
 LaunchFn pick_1d_ng3(int bkg, int obj, bool grad, bool f32);
 LaunchFn pick_1d_ng4(int bkg, int obj, bool grad, bool f32);
-LaunchFn pick_2d(bool grad, bool f32);
+LaunchFn pick_2d(int obj, bool grad, bool f32);
+constexpr int kChunk2D = 16;  // bins of one row per 2D work item
 
 }  // namespace hf

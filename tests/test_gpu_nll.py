@@ -181,8 +181,14 @@ def _case2d(nx, ny, seed):
 def test_nll_grad_2d_parity(hf, orc, obj, prec):
     import torch
     r = (0.0, 1.0, 0.0, 1.0)
-    for nx, ny in ((1, 1), (37, 29), (64, 64), (513, 257)):
+    # (64, 64): 16-bin row pieces too wide for the row recurrence (per-bin
+    # exps) with vector loads; (513, 257): recurrence, scalar loads, short
+    # tail piece per row; (1028, 96): recurrence, vector loads and a 4-bin
+    # tail per row, counts as FP64
+    for nx, ny in ((1, 1), (37, 29), (64, 64), (513, 257), (1028, 96)):
         counts, w, th = _case2d(nx, ny, nx * 1000 + ny)
+        if nx == 1028:
+            counts = counts.astype(np.float64)
         ref = orc.nll_grad(orc.Model(3), obj, counts, th, r, weights=w.astype(np.float64),
                            want_ell=True)
         seed = torch.tensor([0.75], dtype=torch.float64, device="cuda")
