@@ -387,9 +387,16 @@ def bench_learned(args, hf, datagen, np, torch, dev):
     li.fit(fs)
     (_, plain), t_plain = timed(lambda: plain_fit(fs))
     (learned, nfb), t_learned = timed(lambda: li.fit(fs))
+    # the plain fit judges: a learned fit counts if it converged and its final
+    # NLL is within 1e-6 of the plain fit's (equal) or below it by more
+    # (better minimum); the two are also reported apart
     both = (plain.status == 0) & (learned.status == 0)
-    agree = both & ((plain.nll - learned.nll).abs() < 1e-6)
-    n_agree = int(agree.sum().item())
+    dn = learned.nll - plain.nll
+    equal = both & (dn.abs() < 1e-6)
+    better = both & (dn <= -1e-6)
+    n_equal = int(equal.sum().item())
+    n_better = int(better.sum().item())
+    n_agree = n_equal + n_better
     n_plain = int((plain.status == 0).sum().item())
     B = len(c["nbins"])
     print(json.dumps(dict(
@@ -405,7 +412,9 @@ def bench_learned(args, hf, datagen, np, torch, dev):
         plain=dict(fits_per_s=n_plain / t_plain, converged=n_plain, seconds=t_plain,
                    mean_iters=float(plain.iters.float().mean().item()),
                    mean_evals=float(plain.nevals.float().mean().item())),
-        learned=dict(fits_per_s_agreeing=n_agree / t_learned, agreeing=n_agree, seconds=t_learned,
+        learned=dict(fits_per_s_agreeing=n_agree / t_learned, agreeing=n_agree, equal=n_equal,
+                     better=n_better, worse=int((both & (dn >= 1e-6)).sum().item()),
+                     seconds=t_learned,
                      fallbacks=nfb, mean_iters=float(learned.iters.float().mean().item()),
                      mean_evals=float(learned.nevals.float().mean().item())),
         speedup=(n_agree / t_learned) / max(n_plain / t_plain, 1e-30),

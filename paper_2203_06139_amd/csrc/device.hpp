@@ -129,10 +129,31 @@ struct Model2D {
 // --------------------------------------------------------------------------
 // Deterministic reductions.
 // --------------------------------------------------------------------------
+// One DPP move of a double (both 32-bit halves) within each row of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over the 64 lanes of a full wave in a fixed order; the result is
+// wave-uniform.  Within each row of 16 lanes: neighbours (quad_perm
+// [1,0,3,2]), pairs (quad_perm [2,3,0,1]), then rotations by 4 and 8 lanes,
+// after which lane 16 r holds its row's sum; the rows combine as
+// (r0 + r1) + (r2 + r3).  DPP moves and readlanes stay in the VALU, where
+// the LDS round trips of lane shuffles would serialise the wave.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_row<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_row<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_row<0x124>(v);  // row_ror:4
+  v += dpp_row<0x128>(v);  // row_ror:8
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Sums v[0..NV) over the block; on return tot[k] holds the block total of

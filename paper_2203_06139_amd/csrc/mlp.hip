@@ -255,93 +255,151 @@ hipError_t rebin_lognorm(int B, const void* counts, int dtype, const int64_t* of
 }
 
 // Default starting point for Gauss + exp(b0 + b1 t); one block per histogram.
+//   background: mean counts of the first and last ne = max(nb/25, 1) bins
+//     (at least 1), a line through the two edge-block centres;
+//   peak: the window position i in [W, nb - W), W = max(nb/256, 1), with the
+//     largest integer excess e(i) = rint(S(i) - (2W+1) bg(i)), S(i) the sum
+//     of counts over [i - W, i + W] (first such i on ties);
+//   width: walking out from the peak while 2 e >= e_max, the half-maximum
+//     bounds give the FWHM.
+// Each thread takes a contiguous segment of positions and slides the window
+// sum along it (S(i+1) = S(i) + c[i+W+1] - c[i-W]), so the work is linear in
+// nb; the walk becomes a search for the nearest positions left and right of
+// the peak with 2 e < e_max.  Sums of integer-valued counts are exact in
+// FP64 in any order, so every decision matches a direct evaluation; the
+// excess is evaluated without FMA contraction (separate products and sums).
+struct Excess {
+  double bk0, dbk, c0, cden, wlen;
+  __device__ __forceinline__ int64_t operator()(double S, int64_t i) const {
+#pragma clang fp contract(off)
+    const double bg = bk0 + dbk * ((static_cast<double>(i) + 0.5 - c0) / cden);
+    return static_cast<int64_t>(__builtin_rint(S - wlen * bg));
+  }
+};
+
+__device__ __forceinline__ double window_sum(const void* counts, int dtype, int64_t off, int64_t i,
+                                             int64_t W) {
+  double s = 0.0;
+  for (int64_t q = i - W; q <= i + W; ++q) s += count_any(counts, dtype, off + q);
+  return s;
+}
+
 __global__ __launch_bounds__(256) void k_default_starts(const void* counts, int dtype,
                                                         const int64_t* __restrict__ offsets,
                                                         const double* __restrict__ ranges,
                                                         double t_shift, double t_scale,
                                                         double* __restrict__ theta0) {
-  __shared__ int64_t best_e[256];
-  __shared__ int64_t best_i[256];
-  __shared__ double edge[2];
-  __shared__ int64_t bounds[2];
+  __shared__ double red_d[2][256];
+  __shared__ int64_t red_e[256];
+  __shared__ int64_t red_i[256];
+  __shared__ int64_t red_j[256];
   const int b = blockIdx.x;
+  const int t = threadIdx.x;
   const int64_t off = offsets[b];
   const int64_t nb = offsets[b + 1] - off;
   if (nb < 1) {  // empty histogram: no start (uniform over the block)
-    if (threadIdx.x < 5) theta0[static_cast<int64_t>(b) * 5 + threadIdx.x] = __builtin_nan("");
+    if (t < 5) theta0[static_cast<int64_t>(b) * 5 + t] = __builtin_nan("");
     return;
   }
   const double lo = ranges[2 * b], hi = ranges[2 * b + 1];
   const double h = (hi - lo) / static_cast<double>(nb);
   const int64_t ne = nb / 25 > 0 ? nb / 25 : 1;  // 4% of the bins at each edge
-  // edge means (thread 0: left, thread 1: right), summed in bin order
-  if (threadIdx.x < 2) {
-    const int64_t s0 = threadIdx.x == 0 ? 0 : nb - ne;
-    double acc = 0.0;
-    for (int64_t i = s0; i < s0 + ne; ++i) acc += count_any(counts, dtype, off + i);
-    edge[threadIdx.x] = acc / static_cast<double>(ne);
+  // edge sums
+  double sl = 0.0, sr = 0.0;
+  for (int64_t i = t; i < ne; i += 256) {
+    sl += count_any(counts, dtype, off + i);
+    sr += count_any(counts, dtype, off + nb - ne + i);
   }
+  red_d[0][t] = sl;
+  red_d[1][t] = sr;
   __syncthreads();
-  const double bk0 = fmax(edge[0], 1.0), bk1 = fmax(edge[1], 1.0);
-  // background line through the edge-block centres, in counts per bin
-  const double c0 = 0.5 * static_cast<double>(ne), c1 = static_cast<double>(nb) - 0.5 * static_cast<double>(ne);
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      red_d[0][t] += red_d[0][t + w];
+      red_d[1][t] += red_d[1][t + w];
+    }
+    __syncthreads();
+  }
+  const double bk0 = fmax(red_d[0][0] / static_cast<double>(ne), 1.0);
+  const double bk1 = fmax(red_d[1][0] / static_cast<double>(ne), 1.0);
+  const double c0 = 0.5 * static_cast<double>(ne);
+  const double c1 = static_cast<double>(nb) - 0.5 * static_cast<double>(ne);
   const int64_t W = nb / 256 > 1 ? nb / 256 : 1;
-  const double wlen = static_cast<double>(2 * W + 1);
-  // excess E_i = window sum - round(window length x background), integer
+  const Excess ex{bk0, bk1 - bk0, c0, c1 - c0, static_cast<double>(2 * W + 1)};
+  // this thread's segment [p0, p1) of the window positions [W, nb - W)
+  const int64_t nv = nb - 2 * W > 0 ? nb - 2 * W : 0;
+  const int64_t L = (nv + 255) / 256;
+  const int64_t p0 = W + t * L;
+  const int64_t p1 = (W + (t + 1) * L < nb - W) ? W + (t + 1) * L : nb - W;
+  // pass 1: largest excess, first position
   int64_t be = INT64_MIN, bi = 0;
-  for (int64_t i = W + threadIdx.x; i < nb - W; i += blockDim.x) {
-    double sacc = 0.0;
-    for (int64_t q = i - W; q <= i + W; ++q) sacc += count_any(counts, dtype, off + q);
-    const double bg = bk0 + (bk1 - bk0) * ((static_cast<double>(i) + 0.5 - c0) / (c1 - c0));
-    const int64_t e = static_cast<int64_t>(rint(sacc - wlen * bg));
-    if (e > be) {  // strided increasing i: keeps the lowest index of a tie
-      be = e;
-      bi = i;
+  if (p0 < p1) {
+    double S = window_sum(counts, dtype, off, p0, W);
+    for (int64_t i = p0;; ++i) {
+      const int64_t e = ex(S, i);
+      if (e > be) {
+        be = e;
+        bi = i;
+      }
+      if (i + 1 >= p1) break;
+      S += count_any(counts, dtype, off + i + W + 1) - count_any(counts, dtype, off + i - W);
     }
   }
-  best_e[threadIdx.x] = be;
-  best_i[threadIdx.x] = bi;
+  red_e[t] = be;
+  red_i[t] = bi;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     int64_t e = INT64_MIN, idx = nb / 2;
-    for (int t = 0; t < static_cast<int>(blockDim.x); ++t)
-      if (best_e[t] > e || (best_e[t] == e && best_i[t] < idx)) {
-        e = best_e[t];
-        idx = best_i[t];
+    for (int q = 0; q < 256; ++q)  // segments in position order: first max wins
+      if (red_e[q] > e) {
+        e = red_e[q];
+        idx = red_i[q];
       }
     if (e == INT64_MIN) {  // histogram shorter than one window
       e = 0;
       idx = nb / 2;
     }
-    best_e[0] = e;
-    best_i[0] = idx;
+    red_e[0] = e;
+    red_i[0] = idx;
   }
   __syncthreads();
-  const int64_t emax = best_e[0], imax = best_i[0];
-  if (threadIdx.x < 2) {  // walk to the half-maximum on each side
-    const int dir = threadIdx.x == 0 ? -1 : 1;
-    int64_t i = imax;
-    while (true) {
-      const int64_t nxt = i + dir;
-      if (nxt < W || nxt >= nb - W) break;
-      double sacc = 0.0;
-      for (int64_t q = nxt - W; q <= nxt + W; ++q) sacc += count_any(counts, dtype, off + q);
-      const double bg = bk0 + (bk1 - bk0) * ((static_cast<double>(nxt) + 0.5 - c0) / (c1 - c0));
-      const int64_t e = static_cast<int64_t>(rint(sacc - wlen * bg));
-      if (2 * e < emax) break;
-      i = nxt;
+  const int64_t emax = red_e[0], imax = red_i[0];
+  __syncthreads();
+  // pass 2: nearest positions left / right of the peak with 2 e < emax
+  int64_t pl = INT64_MIN, pr = INT64_MAX;
+  if (p0 < p1 && (p0 < imax || p1 - 1 > imax)) {
+    double S = window_sum(counts, dtype, off, p0, W);
+    for (int64_t i = p0;; ++i) {
+      if (i != imax && 2 * ex(S, i) < emax) {
+        if (i < imax) pl = i;                 // keeps the largest below the peak
+        else if (pr == INT64_MAX) pr = i;     // first above the peak
+      }
+      if (i + 1 >= p1 || (i > imax && pr != INT64_MAX)) break;
+      S += count_any(counts, dtype, off + i + W + 1) - count_any(counts, dtype, off + i - W);
     }
-    bounds[threadIdx.x] = i;
   }
+  red_e[t] = pl;
+  red_j[t] = pr;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
+    int64_t l = INT64_MIN, r = INT64_MAX;
+    for (int q = 0; q < 256; ++q) {
+      l = red_e[q] > l ? red_e[q] : l;
+      r = red_j[q] < r ? red_j[q] : r;
+    }
+    // the walk stops just inside the first failing position, or at the edge
+    // of the window range; it never moves when that range is empty
+    const int64_t left = l == INT64_MIN ? W : (l + 1 > W ? l + 1 : W);
+    const int64_t right = r == INT64_MAX ? nb - W - 1 : (r - 1 < nb - W - 1 ? r - 1 : nb - W - 1);
+    const int64_t b0i = left < imax ? left : imax;
+    const int64_t b1i = right > imax ? right : imax;
     const double range = hi - lo;
-    const double fwhm = static_cast<double>(bounds[1] - bounds[0] + 1) * h;
+    const double fwhm = static_cast<double>(b1i - b0i + 1) * h;
     const double s = fmin(fmax(fwhm / 2.3548200450309493, 0.005 * range), 0.1 * range);
-    const double A = fmax(static_cast<double>(emax) / wlen, 1.0);
+    const double A = fmax(static_cast<double>(emax) / ex.wlen, 1.0);
     const double m = lo + (static_cast<double>(imax) + 0.5) * h;
-    const double t0 = (lo + (c0) * h - t_shift) / t_scale;
-    const double t1 = (lo + (c1) * h - t_shift) / t_scale;
+    const double t0 = (lo + c0 * h - t_shift) / t_scale;
+    const double t1 = (lo + c1 * h - t_shift) / t_scale;
     const double b1 = log(bk1 / bk0) / (t1 - t0);
     const double b0v = log(bk0) - b1 * t0;
     double* th = theta0 + static_cast<int64_t>(b) * 5;

@@ -176,14 +176,13 @@ __device__ __forceinline__ void chunk_step(const NllArgs& a, const Model1D<NG, B
 }
 
 // Grid-stride loop over the full chunks of 4-byte counts, with the next chunk
-// loaded while the current one is computed.
+// loaded while the current one is computed.  `nxt` holds the thread's first
+// chunk (chunk tid), loaded by the caller when tid < nfull.
 template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN, bool SPEC, int NV>
 __device__ __forceinline__ void stream_chunks(const NllArgs& a, const Model1D<NG, BKG>& M,
                                               const double2* lut, int64_t nfull, int64_t tid,
-                                              int64_t stride, double seed, double (&acc)[NV],
-                                              int& flags) {
-  ChunkRaw nxt;
-  if (tid < nfull) load_raw<SPEC>(a, tid * kChunk, nxt);
+                                              int64_t stride, double seed, ChunkRaw nxt,
+                                              double (&acc)[NV], int& flags) {
   for (int64_t c = tid; c < nfull; c += stride) {
     const ChunkRaw cur = nxt;
     if (c + stride < nfull) load_raw<SPEC>(a, (c + stride) * kChunk, nxt);
@@ -197,6 +196,20 @@ template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN>
 __global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_1d(NllArgs a) {
   using S = Shape1D<NG, BKG>;
   constexpr int NV = GRAD ? S::P + 1 : 1;
+  const int64_t nb = a.nx;
+  const int64_t nfull = nb / kChunk;
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const bool spec = a.dtype == DT_U32 && !a.weights;
+  // the first chunk's counts are requested before the log table, so the two
+  // memory latencies overlap instead of adding up
+  ChunkRaw first;
+  if (a.dtype != DT_F64 && tid < nfull) {
+    if (spec)
+      load_raw<true>(a, tid * kChunk, first);
+    else
+      load_raw<false>(a, tid * kChunk, first);
+  }
   __shared__ double2 lut[kLogLut];
   if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
   Model1D<NG, BKG> M;
@@ -208,15 +221,13 @@ __global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_1d(NllArgs a) {
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
   const double seed = (a.grad_w_out && a.seed) ? a.seed[0] : 1.0;
-  const int64_t nb = a.nx;
-  const int64_t nfull = nb / kChunk;
-  const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
 
-  if (a.dtype == DT_U32 && !a.weights) {
-    stream_chunks<NG, BKG, OBJ, GRAD, F32BIN, true>(a, M, lut, nfull, tid, stride, seed, acc, flags);
+  if (spec) {
+    stream_chunks<NG, BKG, OBJ, GRAD, F32BIN, true>(a, M, lut, nfull, tid, stride, seed, first, acc,
+                                                    flags);
   } else if (a.dtype != DT_F64) {
-    stream_chunks<NG, BKG, OBJ, GRAD, F32BIN, false>(a, M, lut, nfull, tid, stride, seed, acc, flags);
+    stream_chunks<NG, BKG, OBJ, GRAD, F32BIN, false>(a, M, lut, nfull, tid, stride, seed, first, acc,
+                                                     flags);
   } else {
     for (int64_t c = tid; c < nfull; c += stride) {
       const int64_t i0 = c * kChunk;

@@ -58,6 +58,19 @@ def plain_fit(fs: FitSet, precision=FP32_BIN, polish_edm=1e-3, edm_tol=1e-10, ma
                           max_iter=max_iter)
 
 
+def physical(res, ranges) -> torch.Tensor:
+    """Converged fits whose peak is a peak: mean inside the histogram range,
+    width between 0.1% and 50% of it, positive amplitude.  A fit can also
+    converge with the Gaussian moved off the data (its gradient vanishes
+    there); such fits are no target for a start predictor."""
+    lo, hi = ranges[:, 0], ranges[:, 1]
+    w = hi - lo
+    th = res.theta
+    s = th[:, 2].abs()
+    return ((res.status == FIT_CONVERGED) & (th[:, 0] > 0) & (th[:, 1] >= lo) & (th[:, 1] <= hi)
+            & (s >= 1e-3 * w) & (s <= 0.5 * w) & torch.isfinite(th).all(dim=1))
+
+
 class LearnedInit:
     def __init__(self, device, seed: int = 0, batch: int = 1024):
         self.device = device
@@ -88,7 +101,7 @@ class LearnedInit:
             counts, off, rg, _ = datagen.batch_case_device(seed + c0, B, nbins, self.device)
             fs = FitSet(counts, off.to(self.device), rg.to(self.device))
             _, res = plain_fit(fs)
-            ok = res.status == FIT_CONVERGED
+            ok = physical(res, fs.ranges)
             if c0 == 0:
                 raw = rebin_lognorm(fs.counts, fs.offsets)
                 m, s = column_stats(raw.reshape(-1, 1))
@@ -137,20 +150,26 @@ class LearnedInit:
         return target_to_theta(y[:B].contiguous(), self.t_mean, self.t_std)
 
     def fit(self, fs: FitSet, precision=FP32_BIN, polish_edm=1e-3, edm_tol=1e-10, max_iter=500):
-        """Fit from the learned start; non-converged fits are refitted from
-        the plain start.  Returns (result, number of fallbacks)."""
+        """Fit from the learned start; fits that did not converge to a
+        physical peak (see physical) are refitted from the plain start, and
+        the refit is kept where it converged to a lower NLL.  Iteration and
+        evaluation counts add both attempts.  Returns (result, number of
+        fallbacks)."""
         th0 = self.predict(fs)
         res = fit_batch(fs.counts, fs.offsets, fs.ranges, MODEL, th0, objective=POISSON,
                         precision=precision, polish_edm=polish_edm, edm_tol=edm_tol,
                         max_iter=max_iter)
-        bad = torch.nonzero(res.status != FIT_CONVERGED).reshape(-1)
+        bad = torch.nonzero(~physical(res, fs.ranges)).reshape(-1)
         nbad = int(bad.numel())
         if nbad:
             sub = subset(fs, bad)
             _, rf = plain_fit(sub, precision, polish_edm, edm_tol, max_iter)
-            res.theta[bad] = rf.theta
-            res.nll[bad] = rf.nll
-            res.status[bad] = rf.status
+            first_ok = res.status[bad] == FIT_CONVERGED
+            take = (rf.status == FIT_CONVERGED) & (~first_ok | (rf.nll < res.nll[bad]))
+            idx = bad[take]
+            res.theta[idx] = rf.theta[take]
+            res.nll[idx] = rf.nll[take]
+            res.status[idx] = rf.status[take]
             res.iters[bad] = res.iters[bad] + rf.iters
             res.nevals[bad] = res.nevals[bad] + rf.nevals
         return res, nbad

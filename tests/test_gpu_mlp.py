@@ -82,6 +82,34 @@ def test_rebin_and_starts_match_oracle(hf):
     np.testing.assert_allclose(th0.cpu().numpy(), ref, rtol=1e-10, atol=1e-12)
 
 
+@pytest.mark.parametrize("dtype", ["u32", "f64"])
+def test_default_starts_edge_sizes(hf, dtype):
+    """Window range empty (1, 2 bins) or one position (3), sizes around the
+    256-bin window step, a flat histogram (every excess ties), a peak at the
+    edge, and the largest batch size; integer counts also as FP64."""
+    import torch
+    from oracle import mlp as om
+    rng = np.random.default_rng(77)
+    hists = [np.array([5.0]), np.array([3.0, 9.0]), np.array([1.0, 7.0, 2.0]),
+             np.full(300, 40.0), rng.poisson(20, 255).astype(float), rng.poisson(20, 256).astype(float),
+             rng.poisson(20, 257).astype(float), rng.poisson(20, 511).astype(float)]
+    for nb, m in ((65536, 0.37), (4096, 0.002), (4096, 0.999), (20000, 0.5)):
+        x = (np.arange(nb) + 0.5) / nb
+        hists.append(rng.poisson(300 * np.exp(-0.5 * ((x - m) / 0.02) ** 2) + 50).astype(float))
+    off = np.zeros(len(hists) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([h.size for h in hists])
+    cat = np.concatenate(hists)
+    rg = np.tile([0.0, 1.0], (len(hists), 1))
+    if dtype == "u32":
+        counts = torch.from_numpy(cat.astype(np.uint32).view(np.int32)).cuda()
+    else:
+        counts = torch.from_numpy(cat).cuda()
+    th0 = hf.default_starts(counts, off, rg, hf.Model(hf.GAUSS_EXP, 1, -1))
+    torch.cuda.synchronize()
+    ref = om.default_starts(cat, off, rg)
+    np.testing.assert_allclose(th0.cpu().numpy(), ref, rtol=1e-10, atol=1e-12)
+
+
 def test_target_maps_and_stats(hf):
     import torch
     from oracle import mlp as om
