@@ -161,15 +161,26 @@ int nll_grad(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t ob
 
 /* Options of the fitter: BFGS on the inverse Hessian in scaled coordinates,
  * backtracking Armijo line search (c1 = 1e-4, step halved up to ls_max
- * times), stop when EDM = g^T H g / 2 < max(edm_tol, 4 eps |L|).         */
+ * times), stop when EDM = g^T H g / 2 < max(edm_tol, 4 eps |L|).  The
+ * first inverse Hessian is the identity, or with hessian_init = 1 the
+ * inverse of the expected Hessian (Fisher information) at theta0,
+ *   F = sum_i c_i (dmu_i/dtheta)(dmu_i/dtheta)^T,
+ *   c_i = d^2 l/d mu^2 at n_i = mu_i (1/mu Poisson, 2/mu Pearson, 2/n for
+ *   n > 0 Neyman), bins whose c_i is not finite and positive skipped,
+ * taken by Cholesky in the scaled coordinates; it falls back to the
+ * identity when a pivot is not above 1e-12 times the largest diagonal
+ * entry or a value is not finite.  The first step is then a Fisher-scoring
+ * (Gauss-Newton) step, and no first-update scaling is applied.            */
 typedef struct {
-  int32_t max_iter;    /* iteration limit, >= 1                           */
-  int32_t ls_max;      /* line-search halvings, 1..60                     */
-  int32_t fixed_iters; /* nonzero: ignore the EDM test (timing runs)      */
-  uint32_t free_mask;  /* bit k set: theta_k is fitted; 0 = all           */
-  double edm_tol;      /* convergence threshold on EDM                    */
-  double polish_edm;   /* HF_FP32_BIN: switch to FP64 bins once EDM is
-                          below this (<= 0: never switch)                 */
+  int32_t max_iter;     /* iteration limit, >= 1                          */
+  int32_t ls_max;       /* line-search halvings, 1..60                    */
+  int32_t fixed_iters;  /* nonzero: ignore the EDM test (timing runs)     */
+  uint32_t free_mask;   /* bit k set: theta_k is fitted; 0 = all          */
+  double edm_tol;       /* convergence threshold on EDM                   */
+  double polish_edm;    /* HF_FP32_BIN: switch to FP64 bins once EDM is
+                           below this (<= 0: never switch)                */
+  int32_t hessian_init; /* 0: identity; 1: inverse expected Hessian       */
+  int32_t reserved;     /* must be 0                                      */
 } hf_fit_opts;
 
 /* Per-fit status codes written to status[b] by fit_batch.                */
@@ -250,11 +261,13 @@ int hf_rebin_lognorm(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t 
 /* The plain method's starting point for one Gaussian + exp(b0 + b1 t)
  * (model: HF_GAUSS_EXP, n_gauss = 1), per histogram of a batch laid out as
  * in fit_batch:
- *   background: mean counts of the first and last 4% of the bins (at least
- *     one bin, floored at 1), an exponential through the two block centres;
- *   peak: the largest integer excess E_i = window sum - rint((2W+1) x the
- *     linear interpolation of the two edge means), window 2W+1 bins with
- *     W = max(1, nbins/256), lowest index on ties; A = max(E/(2W+1), 1);
+ *   background: mean counts bk0, bk1 of the first and last 4% of the bins
+ *     (at least one bin, floored at 1), an exponential through the two
+ *     block centres c0, c1: bg_i = exp(ln bk0 + (ln bk1 - ln bk0)
+ *     (i + 1/2 - c0)/(c1 - c0)) in counts per bin;
+ *   peak: the largest integer excess E_i = rint(S_i - (2W+1) bg_i), S_i the
+ *     sum of the counts of bins i-W..i+W, W = max(1, nbins/256), over
+ *     W <= i < nbins - W, lowest index on ties; A = max(E/(2W+1), 1);
  *   width: the excess walked outwards from the peak until 2 E < E_max gives
  *     the FWHM; s = FWHM/2.3548 clamped to [0.005, 0.1] of the range.
  * theta0: device f64[B][5] (A, m, s, b0, b1).                              */

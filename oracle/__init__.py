@@ -48,7 +48,8 @@ class _Model(ctypes.Structure):
 class _FitOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("ls_max", ctypes.c_int32),
                 ("fixed_iters", ctypes.c_int32), ("free_mask", ctypes.c_uint32),
-                ("edm_tol", ctypes.c_double)]
+                ("edm_tol", ctypes.c_double), ("hessian_init", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -86,6 +87,8 @@ def lib():
         L.or_nll_grad_mt.argtypes = [mp, ctypes.c_int, dp, dp, ctypes.c_int64, ctypes.c_int64, dp,
                                      dp, dp, dp, dp, dp, ip, ctypes.c_int]
         L.or_nll_grad_mt.restype = ctypes.c_int
+        L.or_fisher.argtypes = [mp, ctypes.c_int, dp, dp, ctypes.c_int64, ctypes.c_int64, dp, dp, dp]
+        L.or_fisher.restype = ctypes.c_int
         L.or_fit_mt.argtypes = [mp, ctypes.c_int, dp, dp, ctypes.c_int64, ctypes.c_int64, dp, dp,
                                 ctypes.POINTER(_FitOpts), dp, dp, ip, ip, ip, ctypes.c_int]
         L.or_fit_mt.restype = ctypes.c_int
@@ -120,6 +123,24 @@ def nparams(model: Model) -> int:
 def neumaier_sum(v) -> float:
     v = _f64(v)
     return lib().or_neumaier_sum(_dp(v), v.size)
+
+
+def fisher(model: Model, objective: int, counts, theta, range4, weights=None):
+    """Expected Hessian F = sum_i w_i c_i (dmu_i/dtheta)(dmu_i/dtheta)^T
+    (c_i = d2l/dmu2 at n_i = mu_i), P x P."""
+    c = np.asarray(counts)
+    nx = c.shape[-1]
+    ny = c.shape[0] if c.ndim == 2 else 1
+    c = _f64(c).reshape(-1)
+    w = _f64(np.asarray(weights).reshape(-1)) if weights is not None else None
+    P = nparams(model)
+    F = np.empty(P * P, dtype=np.float64)
+    m = model.c()
+    rc = lib().or_fisher(ctypes.byref(m), objective, _dp(c), _dp(w), nx, ny, _dp(_range4(range4)),
+                         _dp(_f64(theta)), _dp(F))
+    if rc != 0:
+        raise ValueError("or_fisher failed: %d" % rc)
+    return F.reshape(P, P)
 
 
 def model_eval(model: Model, theta, shape, range4):
@@ -182,7 +203,8 @@ class FitResult:
 
 
 def fit(model: Model, objective: int, counts, theta0, range4, weights=None, max_iter=500,
-        edm_tol=1e-10, ls_max=30, fixed_iters=False, free_mask=0, nthreads=1) -> FitResult:
+        edm_tol=1e-10, ls_max=30, fixed_iters=False, free_mask=0, nthreads=1,
+        hessian_init=0) -> FitResult:
     c = np.asarray(counts)
     nx = c.shape[-1]
     ny = c.shape[0] if c.ndim == 2 else 1
@@ -191,7 +213,7 @@ def fit(model: Model, objective: int, counts, theta0, range4, weights=None, max_
     th0 = _f64(theta0)
     P = nparams(model)
     r = _range4(range4)
-    opts = _FitOpts(max_iter, ls_max, 1 if fixed_iters else 0, free_mask, edm_tol)
+    opts = _FitOpts(max_iter, ls_max, 1 if fixed_iters else 0, free_mask, edm_tol, hessian_init, 0)
     out = np.empty(P, dtype=np.float64)
     nll = ctypes.c_double()
     st, it, ne = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -205,7 +227,7 @@ def fit(model: Model, objective: int, counts, theta0, range4, weights=None, max_
 
 
 def fit_many(model: Model, objective: int, counts_concat, offsets, ranges, theta0, max_iter=500,
-             edm_tol=1e-10, ls_max=30, nthreads=1):
+             edm_tol=1e-10, ls_max=30, nthreads=1, hessian_init=0):
     """Independent fits of B histograms stored end to end; returns arrays."""
     c = _f64(counts_concat)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -213,7 +235,7 @@ def fit_many(model: Model, objective: int, counts_concat, offsets, ranges, theta
     th0 = _f64(theta0).reshape(-1)
     B = off.size - 1
     P = nparams(model)
-    opts = _FitOpts(max_iter, ls_max, 0, 0, edm_tol)
+    opts = _FitOpts(max_iter, ls_max, 0, 0, edm_tol, hessian_init, 0)
     out = np.empty(B * P, dtype=np.float64)
     nll = np.empty(B, dtype=np.float64)
     st = np.empty(B, dtype=np.int32)

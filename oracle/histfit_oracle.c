@@ -50,7 +50,10 @@
  * minimum EDM = g^T H g / 2 (Nocedal & Wright, "Numerical Optimization",
  * ch. 6, with the first-step scaling of their eq. 6.20).  The stopping
  * threshold is max(edm_tol, 4 eps |f|): below a few ulps of the objective a
- * decrease can no longer be verified.
+ * decrease can no longer be verified.  Optionally the first inverse Hessian
+ * is the inverse of the expected Hessian (Fisher information, or_fisher) at
+ * the start instead of the identity, so the first step is a Gauss-Newton
+ * (Fisher scoring) step; the eq. 6.20 scaling is then skipped.
  *
  * The MLP routines (or_mlp_*) are the plain forward and backward passes of a
  * dense GELU network with bfloat16 rounding applied at stated points; they
@@ -415,7 +418,82 @@ typedef struct {
   int32_t fixed_iters; /* nonzero: ignore the EDM test, run max_iter steps */
   uint32_t free_mask;  /* bit k set: theta_k is free; 0 means all free   */
   double edm_tol;
+  int32_t hessian_init; /* 0: H = I; 1: H = inverse expected Hessian at theta0 */
+  int32_t reserved;
 } or_fit_opts;
+
+/* Expected Hessian (Fisher information) of L = sum_i w_i l_i:
+ *   F = sum_i w_i c_i (dmu_i/dtheta)(dmu_i/dtheta)^T
+ * with c_i = d^2 l / d mu^2 at n_i = mu_i: 1/mu_i (Poisson), 2/n_i for
+ * n_i > 0 (Neyman; empty bins are skipped), 2/mu_i (Pearson).  Where the
+ * counts equal the model this is the exact Hessian, because the second
+ * derivatives of mu are multiplied by dl/dmu = 0.  Bins whose c_i is not a
+ * finite positive number (mu <= 0) contribute nothing.  F_out is row-major
+ * P x P, each entry a Neumaier sum in bin order.  Returns 0, or -1/-2 on
+ * bad arguments.                                                         */
+int or_fisher(const or_model* m, int obj, const double* counts, const double* weights, int64_t nx,
+              int64_t ny, const double* range4, const double* theta, double* F_out) {
+  int P = or_nparams(m);
+  if (P < 0 || P > OR_MAXP) return -2;
+  if (!counts || !range4 || !theta || !F_out || nx <= 0 || ny <= 0) return -1;
+  nsum* acc = (nsum*)calloc((size_t)P * (size_t)P, sizeof(nsum));
+  if (!acc) return -1;
+  double dmu[OR_MAXP];
+  for (int64_t i = 0; i < nx * ny; ++i) {
+    double n = counts[i];
+    double w = weights ? weights[i] : 1.0;
+    double mu = eval_mu(m, theta, nx, ny, range4, i, dmu);
+    double c;
+    if (obj == OR_POISSON) c = 1.0 / mu;
+    else if (obj == OR_PEARSON) c = 2.0 / mu;
+    else c = (n > 0.0) ? 2.0 / n : 0.0;
+    if (!(c > 0.0) || !isfinite(c)) continue;
+    for (int a = 0; a < P; ++a)
+      for (int b = 0; b < P; ++b) nsum_add(&acc[a * P + b], w * c * dmu[a] * dmu[b]);
+  }
+  for (int a = 0; a < P * P; ++a) F_out[a] = nsum_value(&acc[a]);
+  free(acc);
+  return 0;
+}
+
+/* Inverse of the symmetric n x n matrix A (row-major) by Cholesky,
+ * A = L L^T, then inv(A) = inv(L)^T inv(L).  Fails (returns 0) when a pivot
+ * is not above 1e-12 times the largest diagonal entry or anything is not
+ * finite; returns 1 with the inverse in Ainv otherwise.                   */
+static int spd_inverse(const double* A, int n, double* Ainv) {
+  double L[OR_MAXP * OR_MAXP] = {0}, Li[OR_MAXP * OR_MAXP] = {0};
+  double dmax = 0.0;
+  for (int a = 0; a < n; ++a) dmax = fmax(dmax, A[a * n + a]);
+  if (!(dmax > 0.0) || !isfinite(dmax)) return 0;
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 1e-12 * dmax) || !isfinite(d)) return 0;
+    L[j * n + j] = sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = v / L[j * n + j];
+    }
+  }
+  /* inv(L) by forward substitution, column by column */
+  for (int c = 0; c < n; ++c) {
+    for (int i = c; i < n; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) v -= L[i * n + k] * Li[k * n + c];
+      Li[i * n + c] = v / L[i * n + i];
+    }
+  }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      double v = 0.0;
+      for (int k = (a > b ? a : b); k < n; ++k) v += Li[k * n + a] * Li[k * n + b];
+      Ainv[a * n + b] = v;
+    }
+  for (int a = 0; a < n * n; ++a)
+    if (!isfinite(Ainv[a])) return 0;
+  return 1;
+}
 
 enum { OR_FIT_CONVERGED = 0, OR_FIT_MAXITER = 1, OR_FIT_LSFAIL = 2, OR_FIT_NONFINITE = 3,
        OR_FIT_DOMAIN = 4 };
@@ -519,6 +597,21 @@ int or_fit_mt(const or_model* m, int obj, const double* counts, const double* we
   for (int a = 0; a < nf * nf; ++a) H[a] = 0.0;
   for (int a = 0; a < nf; ++a) H[a * nf + a] = 1.0;
   int first_update = 1;
+  if (opts->hessian_init == 1 && nf > 0) {
+    /* H = inverse of the expected Hessian at theta0 in the internal
+     * coordinates (F_u = diag(sigma) F diag(sigma) over the free
+     * parameters); identity when F_u is not safely positive definite.   */
+    double F[OR_MAXP * OR_MAXP], Fu[OR_MAXP * OR_MAXP], Hi[OR_MAXP * OR_MAXP];
+    if (or_fisher(m, obj, counts, weights, nx, ny, range4, theta0, F) == 0) {
+      for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b)
+          Fu[a * nf + b] = sig[fidx[a]] * sig[fidx[b]] * F[fidx[a] * P + fidx[b]];
+      if (spd_inverse(Fu, nf, Hi)) {
+        for (int a = 0; a < nf * nf; ++a) H[a] = Hi[a];
+        first_update = 0;
+      }
+    }
+  }
 
   double f = fit_eval(&fp, u, g, th);
   int status = OR_FIT_MAXITER;

@@ -149,9 +149,13 @@ def default_starts(counts_concat, offsets, ranges, t_shift=0.0, t_scale=1.0):
         W = max(nb // 256, 1)
         wlen = 2 * W + 1
 
+        lb0 = math.log(bk0)
+        dlb = math.log(bk1) - lb0
+
         def excess(i):
+            # window sum minus the exponential background through the edge means
             s = c[i - W:i + W + 1].sum()
-            bg = bk0 + (bk1 - bk0) * ((i + 0.5 - c0) / (c1 - c0))
+            bg = math.exp(lb0 + dlb * ((i + 0.5 - c0) / (c1 - c0)))
             return int(np.rint(s - wlen * bg))
 
         best, imax = None, nb // 2

@@ -27,6 +27,7 @@ FP64, FP32_BIN = 0, 1
 U32, F32, F64 = 0, 1, 2
 ST_DOMAIN, ST_NONFINITE = 1, 2
 FIT_CONVERGED, FIT_MAXITER, FIT_LSFAIL, FIT_NONFINITE, FIT_DOMAIN, FIT_BADHIST = range(6)
+IDENTITY, FISHER = 0, 1  # fit_batch hessian_init
 
 
 class HfModel(ctypes.Structure):
@@ -46,7 +47,8 @@ class HfHist(ctypes.Structure):
 class HfFitOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("ls_max", ctypes.c_int32),
                 ("fixed_iters", ctypes.c_int32), ("free_mask", ctypes.c_uint32),
-                ("edm_tol", ctypes.c_double), ("polish_edm", ctypes.c_double)]
+                ("edm_tol", ctypes.c_double), ("polish_edm", ctypes.c_double),
+                ("hessian_init", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -315,8 +317,10 @@ class FitBatchResult:
 
 def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=POISSON,
               precision=FP64, max_iter=500, ls_max=30, fixed_iters=False, free_mask=0,
-              edm_tol=1e-10, polish_edm=0.0, out: FitBatchResult | None = None):
-    """Fit B histograms laid end to end in counts_concat; device tensors out."""
+              edm_tol=1e-10, polish_edm=0.0, hessian_init=FISHER,
+              out: FitBatchResult | None = None):
+    """Fit B histograms laid end to end in counts_concat; device tensors out.
+    hessian_init: IDENTITY or FISHER (inverse expected Hessian at theta0)."""
     import torch
     c = counts_concat
     dev = c.device
@@ -341,7 +345,8 @@ def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=PO
                              torch.empty(B, dtype=torch.int32, device=dev),
                              torch.empty(B, dtype=torch.int32, device=dev),
                              torch.empty(B, dtype=torch.int32, device=dev))
-    opts = HfFitOpts(max_iter, ls_max, 1 if fixed_iters else 0, free_mask, edm_tol, polish_edm)
+    opts = HfFitOpts(max_iter, ls_max, 1 if fixed_iters else 0, free_mask, edm_tol, polish_edm,
+                     int(hessian_init), 0)
     rc = load().fit_batch(ctx, B, _ptr(c), _dtype_code(c), _ptr(off), _ptr(rg),
                           ctypes.byref(model.c()), objective, precision, _ptr(th0),
                           ctypes.byref(opts), _ptr(out.theta), _ptr(out.nll), _ptr(out.status),

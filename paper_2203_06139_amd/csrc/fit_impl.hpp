@@ -5,12 +5,16 @@
 // "Numerical Optimization", ch. 6 and eq. 6.20):
 //   scaled coordinates u_k = (theta_k - theta0_k)/sigma_k for the free
 //   parameters, sigma by parameter kind (amplitude max(|A0|,1), mean
-//   range/100, width |s0|, background max(|c0|,1));  H = I;
+//   range/100, width |s0|, background max(|c0|,1));  H = I, or with the
+//   Fisher start H = inverse expected Hessian at theta0 (Gauss-Newton /
+//   Fisher scoring first step; identity if it is not safely positive
+//   definite);
 //   repeat: p = -H g;  EDM = g^T H g / 2;  stop when EDM < max(edm_tol,
 //   4 eps |f|);  if g^T p >= 0 restart from H = I;  backtracking Armijo
 //   (c1 = 1e-4, alpha halved up to ls_max times; non-finite f rejected);
 //   s = alpha p, y = g_new - g;  if s^T y > 1e-12 |s||y| the BFGS inverse
-//   update (scaled by s^T y / y^T y before the first one).
+//   update (scaled by s^T y / y^T y before the first one after an identity
+//   start).
 // Finally |s| for every width, Gaussians ordered by mean, and the NLL
 // re-evaluated with FP64 bins.
 //
@@ -39,20 +43,45 @@ __device__ __forceinline__ double count_at(const void* base, int dtype, int64_t 
   return static_cast<const double*>(base)[i];
 }
 
+// Entries of the expected Hessian accumulated per pass over the bins.
+constexpr int kFisherPass = 32;
+
 template <int NG, int BKG>
 struct FitShared {
   static constexpr int P = Shape1D<NG, BKG>::P;
   static constexpr int NV = P + 1;
   double th[P], th0[P], sig[P];
   double u[P], g[P], un[P], gn[P], pv[P], tmp[P], sv[P], yv[P], Hy[P];
-  double H[P * P];  // row stride P; the leading nf x nf block is used
+  double H[P * P];   // row stride P; the leading nf x nf block is used
+  double Lc[P * P];  // Fisher start: scaled F, its Cholesky factor, the inverse
   double tot[NV];
   double red[kWaves][NV];
+  double fred[kWaves * kFisherPass];
+  double ftot[kFisherPass];
+  double dmax;
   int redf[kWaves];
-  int totf;
+  int fredf[kWaves];
+  int totf, ftotf;
+  int chol_ok;
   int fidx[P];
   int nf;
   int h;
+};
+
+// Row and column of entry e of the upper triangle of a P x P matrix,
+// row-major (a <= b).
+template <int P>
+struct TriIndex {
+  static constexpr int N = P * (P + 1) / 2;
+  int a[N], b[N];
+  constexpr TriIndex() : a(), b() {
+    int e = 0;
+    for (int r = 0; r < P; ++r)
+      for (int c = r; c < P; ++c, ++e) {
+        a[e] = r;
+        b[e] = c;
+      }
+  }
 };
 
 // Bins per thread per step of the fit's objective sweep.
@@ -110,6 +139,153 @@ __device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
   if (threadIdx.x >= 1 && threadIdx.x < NV) sm.tot[threadIdx.x] *= M.final_factor(threadIdx.x);
   if (threadIdx.x == 0 && (sm.totf & ST_DOMAIN)) sm.tot[0] = __builtin_inf();
   __syncthreads();
+}
+
+// mu(x) and dmu/dtheta by their closed forms, one exp per Gaussian (the
+// Fisher pass runs once per fit, so it does without the recurrence):
+//   dG/dA = e, dG/dm = G z / s, dG/ds = G z^2 / s with z = (x - m)/s;
+//   polynomial t^j; exponential E and t E.
+template <int NG, int BKG>
+__device__ __forceinline__ double mu_partials(const Model1D<NG, BKG>& M, double x,
+                                              double (&v)[Shape1D<NG, BKG>::P]) {
+  using S = Shape1D<NG, BKG>;
+  double mu = 0.0;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const double z = (x - M.m[g]) * M.is[g];
+    const double e = exp(-0.5 * z * z);
+    const double G = M.A[g] * e;
+    mu += G;
+    v[3 * g] = e;
+    v[3 * g + 1] = G * z * M.is[g];
+    v[3 * g + 2] = G * z * z * M.is[g];
+  }
+  const double t = (x - M.tshift) * M.ta;
+  if constexpr (BKG == BKG_EXP) {
+    const double E = exp(fma(M.c[1], t, M.c[0]));
+    mu += E;
+    v[3 * NG] = E;
+    v[3 * NG + 1] = t * E;
+  } else if constexpr (S::NB > 0) {
+    double tj = 1.0;
+#pragma unroll
+    for (int j = 0; j < S::NB; ++j) {
+      mu = fma(M.c[j], tj, mu);
+      v[3 * NG + j] = tj;
+      tj *= t;
+    }
+  }
+  return mu;
+}
+
+// Expected Hessian at theta0, F = sum_i c_i (dmu_i/dtheta)(dmu_i/dtheta)^T
+// with c_i = d^2 l/d mu^2 at n_i = mu_i (1/mu Poisson, 2/mu Pearson, 2/n for
+// n > 0 Neyman); bins whose c_i is not finite and positive are skipped.  The
+// upper triangle is accumulated kFisherPass entries per pass over the bins
+// and written symmetrically into sm.H.
+template <int NG, int BKG, int OBJ, int PASS>
+__device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG>& sm, const CountsSrc& src,
+                            int64_t nb, double x0, double hx) {
+  constexpr int P = FitShared<NG, BKG>::P;
+  constexpr TriIndex<P> tri{};
+  constexpr int E0 = PASS * kFisherPass;
+  if constexpr (E0 < TriIndex<P>::N) {
+    constexpr int NQ = (TriIndex<P>::N - E0 < kFisherPass) ? TriIndex<P>::N - E0 : kFisherPass;
+    Model1D<NG, BKG> M;
+    M.init(sm.th0, a.t_shift, a.t_scale);
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += kBlock) {
+      double v[P];
+      const double mu = mu_partials(M, fma(static_cast<double>(i), hx, x0), v);
+      double c;
+      if constexpr (OBJ == OBJ_POISSON) c = 1.0 / mu;
+      else if constexpr (OBJ == OBJ_PEARSON) c = 2.0 / mu;
+      else {
+        const double n = src.at(i);
+        c = n > 0.0 ? 2.0 / n : 0.0;
+      }
+      if (c > 0.0 && __builtin_isfinite(c)) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = fma(c * v[tri.a[E0 + q]], v[tri.b[E0 + q]], acc[q]);
+      }
+    }
+    block_sum<NQ>(acc, 0, sm.ftot, &sm.ftotf, reinterpret_cast<double(*)[NQ]>(sm.fred), sm.fredf);
+    if (threadIdx.x < NQ) {
+      const int r = tri.a[E0 + threadIdx.x], c = tri.b[E0 + threadIdx.x];
+      sm.H[r * P + c] = sm.ftot[threadIdx.x];
+      sm.H[c * P + r] = sm.ftot[threadIdx.x];
+    }
+    fisher_pass<NG, BKG, OBJ, PASS + 1>(a, sm, src, nb, x0, hx);
+  }
+}
+
+// Replaces the identity in sm.H by the inverse of F_u = diag(sigma) F
+// diag(sigma) over the free parameters, F already in sm.H: Cholesky
+// F_u = L L^T (a pivot must exceed 1e-12 times the largest diagonal entry),
+// inv(L) by forward substitution, H = inv(L)^T inv(L).  Falls back to the
+// identity when F_u is not safely positive definite or anything is not
+// finite.  Returns whether the inverse was taken.
+template <int NG, int BKG>
+__device__ bool fisher_start(FitShared<NG, BKG>& sm, int nf) {
+  constexpr int P = FitShared<NG, BKG>::P;
+  const int tid = threadIdx.x;
+  __syncthreads();
+  for (int t = tid; t < nf * nf; t += kBlock) {
+    const int r = t / nf, c = t % nf;
+    sm.Lc[r * P + c] = sm.sig[sm.fidx[r]] * sm.sig[sm.fidx[c]] * sm.H[sm.fidx[r] * P + sm.fidx[c]];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double dmax = 0.0;
+    for (int r = 0; r < nf; ++r) dmax = fmax(dmax, sm.Lc[r * P + r]);
+    sm.dmax = dmax;
+    sm.chol_ok = (dmax > 0.0 && __builtin_isfinite(dmax)) ? 1 : 0;
+  }
+  __syncthreads();
+  const double dmax = sm.dmax;
+  for (int j = 0; j < nf && sm.chol_ok; ++j) {
+    if (tid == 0) {
+      double d = sm.Lc[j * P + j];
+      for (int k = 0; k < j; ++k) d -= sm.Lc[j * P + k] * sm.Lc[j * P + k];
+      if (!(d > 1e-12 * dmax) || !__builtin_isfinite(d)) sm.chol_ok = 0;
+      else sm.Lc[j * P + j] = sqrt(d);
+    }
+    __syncthreads();
+    if (sm.chol_ok && tid > j && tid < nf) {
+      double v = sm.Lc[tid * P + j];
+      for (int k = 0; k < j; ++k) v -= sm.Lc[tid * P + k] * sm.Lc[j * P + k];
+      sm.Lc[tid * P + j] = v / sm.Lc[j * P + j];
+    }
+    __syncthreads();
+  }
+  if (sm.chol_ok) {
+    if (tid < nf) {  // column tid of inv(L), into the lower triangle of H
+      const int c = tid;
+      for (int i = c; i < nf; ++i) {
+        double v = (i == c) ? 1.0 : 0.0;
+        for (int k = c; k < i; ++k) v -= sm.Lc[i * P + k] * sm.H[k * P + c];
+        sm.H[i * P + c] = v / sm.Lc[i * P + i];
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < nf * nf; t += kBlock) {
+      const int r = t / nf, c = t % nf;
+      double v = 0.0;
+      for (int k = (r > c ? r : c); k < nf; ++k) v += sm.H[k * P + r] * sm.H[k * P + c];
+      sm.Lc[r * P + c] = v;
+      if (!__builtin_isfinite(v)) sm.chol_ok = 0;
+    }
+    __syncthreads();
+  }
+  const bool ok = sm.chol_ok != 0;
+  for (int t = tid; t < P * P; t += kBlock) {
+    const int r = t / P, c = t % P;
+    sm.H[t] = (ok && r < nf && c < nf) ? sm.Lc[r * P + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  return ok;
 }
 
 // f(u) and g_u = sigma * dL/dtheta at theta = theta0 + sigma * u.
@@ -188,11 +364,15 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
   for (int t = tid; t < P * P; t += kBlock) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
   __syncthreads();
   const int nf = sm.nf;
+  bool first = true;
+  if (a.hessian_init == 1 && nf > 0) {
+    fisher_pass<NG, BKG, OBJ, 0>(a, sm, src, nb, x0, hx);
+    first = !fisher_start(sm, nf);  // no first-update scaling after a Fisher start
+  }
 
   bool f32 = a.f32 != 0;
   double f = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.u, sm.g, f32, nb, x0, hx);
   int nev = 1, it = 0, status = FIT_MAXITER;
-  bool first = true;
   if (!__builtin_isfinite(f)) {
     status = (f == __builtin_inf()) ? FIT_DOMAIN : FIT_NONFINITE;
   } else {

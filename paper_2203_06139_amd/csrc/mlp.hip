@@ -256,7 +256,9 @@ hipError_t rebin_lognorm(int B, const void* counts, int dtype, const int64_t* of
 
 // Default starting point for Gauss + exp(b0 + b1 t); one block per histogram.
 //   background: mean counts of the first and last ne = max(nb/25, 1) bins
-//     (at least 1), a line through the two edge-block centres;
+//     (at least 1), an exponential through the two edge-block centres (the
+//     model's own background form; a straight line would leave a false
+//     excess at the steep edge of a falling or rising background);
 //   peak: the window position i in [W, nb - W), W = max(nb/256, 1), with the
 //     largest integer excess e(i) = rint(S(i) - (2W+1) bg(i)), S(i) the sum
 //     of counts over [i - W, i + W] (first such i on ties);
@@ -269,10 +271,10 @@ hipError_t rebin_lognorm(int B, const void* counts, int dtype, const int64_t* of
 // FP64 in any order, so every decision matches a direct evaluation; the
 // excess is evaluated without FMA contraction (separate products and sums).
 struct Excess {
-  double bk0, dbk, c0, cden, wlen;
+  double lb0, dlb, c0, cden, wlen;
   __device__ __forceinline__ int64_t operator()(double S, int64_t i) const {
 #pragma clang fp contract(off)
-    const double bg = bk0 + dbk * ((static_cast<double>(i) + 0.5 - c0) / cden);
+    const double bg = exp(lb0 + dlb * ((static_cast<double>(i) + 0.5 - c0) / cden));
     return static_cast<int64_t>(__builtin_rint(S - wlen * bg));
   }
 };
@@ -325,7 +327,8 @@ __global__ __launch_bounds__(256) void k_default_starts(const void* counts, int 
   const double c0 = 0.5 * static_cast<double>(ne);
   const double c1 = static_cast<double>(nb) - 0.5 * static_cast<double>(ne);
   const int64_t W = nb / 256 > 1 ? nb / 256 : 1;
-  const Excess ex{bk0, bk1 - bk0, c0, c1 - c0, static_cast<double>(2 * W + 1)};
+  const double lb0 = log(bk0);
+  const Excess ex{lb0, log(bk1) - lb0, c0, c1 - c0, static_cast<double>(2 * W + 1)};
   // this thread's segment [p0, p1) of the window positions [W, nb - W)
   const int64_t nv = nb - 2 * W > 0 ? nb - 2 * W : 0;
   const int64_t L = (nv + 255) / 256;

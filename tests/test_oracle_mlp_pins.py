@@ -109,3 +109,19 @@ def test_target_maps_round_trip():
     mu, sd = om.column_stats(t)
     np.testing.assert_allclose(mu, t.mean(axis=0), rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(sd, t.std(axis=0), rtol=1e-12)
+
+
+def test_default_starts_steep_background_has_no_false_edge_peak():
+    """Backgrounds rising 20x to 100x across the range with a peak inside:
+    against a straight line through the edge means the convex background
+    itself leaves the largest excess at the steep edge (x = 0.996 in every
+    case below); against the exponential through the edge means the start
+    lands on the peak and b1 on the background slope."""
+    nb = 16384
+    x = (np.arange(nb) + 0.5) / nb
+    for A, m, s, rise in ((120, 0.5, 0.02, 46), (60, 0.4, 0.03, 46), (200, 0.3, 0.02, 100),
+                          (40, 0.5, 0.02, 20)):
+        c = np.rint(A * np.exp(-0.5 * ((x - m) / s) ** 2) + 20.0 * np.exp(math.log(rise) * x))
+        th = om.default_starts(c, [0, nb], [(0.0, 1.0)])[0]
+        assert abs(th[1] - m) < 0.005, (A, m, s, rise, th)
+        assert th[4] == pytest.approx(math.log(rise), rel=0.02), (A, m, s, rise, th)

@@ -402,3 +402,98 @@ def test_fig2a_workload_fit(orc):
     phi = lambda z: 0.5 * (1 + math.erf(z / math.sqrt(2)))
     inside = phi((5 - 1) / 3) - phi((-5 - 1) / 3)
     assert A * s * math.sqrt(2 * math.pi) / 0.01 == pytest.approx(c["counts"].sum() / inside, rel=0.02)
+
+
+# ---------------------------------------------------------------------------
+# Expected Hessian (Fisher start of the fitter)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("obj", [0, 1, 2])
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_fisher_is_the_hessian_at_noiseless_truth(orc, obj, case):
+    """Where the counts equal the model, dl/dmu = 0 removes the second
+    derivatives of mu from the Hessian, so F must equal it.  The Hessian here
+    is a central difference of the complex-step gradient of the independent
+    numpy forward pass."""
+    spec, th, r = CASES_1D[case]
+    M = om(orc, spec)
+    th = np.array(th)
+    n = orc.model_eval(M, th, (300,), r)
+    F = orc.fisher(M, obj, n, th, r)
+    H = np.empty_like(F)
+    for k in range(th.size):
+        h = 1e-4 * max(abs(th[k]), 1e-2)
+        e = np.zeros_like(th)
+        e[k] = h
+        H[:, k] = (complex_step_grad(spec, obj, n, th + e, r) -
+                   complex_step_grad(spec, obj, n, th - e, r)) / (2 * h)
+    H = 0.5 * (H + H.T)
+    d = np.sqrt(np.outer(np.abs(np.diag(H)), np.abs(np.diag(H))))
+    assert np.all(np.abs(F - H) <= 1e-5 * d), np.max(np.abs(F - H) / d)
+
+
+def test_fisher_2d_is_the_hessian_at_noiseless_truth(orc):
+    spec = dict(kind=3)
+    M = orc.Model(3)
+    th = np.array([500.0, 0.4, 0.6, 0.1, 0.12, -0.35, 7.0])
+    r = (0, 1, 0, 1)
+    n = orc.model_eval(M, th, (24, 24), r)
+    for obj in (0, 1, 2):
+        F = orc.fisher(M, obj, n, th, r)
+        H = np.empty_like(F)
+        for k in range(th.size):
+            h = 1e-4 * max(abs(th[k]), 1e-2)
+            e = np.zeros_like(th)
+            e[k] = h
+            H[:, k] = (complex_step_grad(spec, obj, n, th + e, r) -
+                       complex_step_grad(spec, obj, n, th - e, r)) / (2 * h)
+        H = 0.5 * (H + H.T)
+        d = np.sqrt(np.outer(np.abs(np.diag(H)), np.abs(np.diag(H))))
+        assert np.all(np.abs(F - H) <= 1e-5 * d), (obj, np.max(np.abs(F - H) / d))
+
+
+def test_fisher_constant_model_closed_form(orc):
+    rng = np.random.default_rng(21)
+    n = rng.poisson(40.0, 400).astype(np.float64)
+    n[:7] = 0
+    w = rng.uniform(0.5, 1.5, n.size)
+    M = _const_model(orc)
+    c = 37.0
+    closed = {2: np.sum(w) / c, 1: 2 * np.sum(w) / c, 0: 2 * np.sum(w[n > 0] / n[n > 0])}
+    for obj, val in closed.items():
+        F = orc.fisher(M, obj, n, [c], (0, 1), weights=w)
+        assert F.shape == (1, 1)
+        assert F[0, 0] == pytest.approx(val, rel=1e-13), obj
+
+
+def test_fisher_scoring_step_is_the_poisson_constant_mle(orc):
+    """For mu = c the Fisher-scoring step from any c0 > 0 lands on the
+    weighted mean: c1 = c0 - g/F = sum(w n)/sum(w).  So the Fisher-started
+    fit takes one iteration."""
+    rng = np.random.default_rng(22)
+    n = rng.poisson(25.0, 300).astype(np.float64)
+    w = rng.uniform(0.5, 1.5, n.size)
+    M = _const_model(orc)
+    c_hat = np.sum(w * n) / np.sum(w)
+    for c0 in (3.0, 20.0, 90.0):
+        fr = orc.fit(M, 2, n, [c0], (0, 1), weights=w, edm_tol=1e-22, hessian_init=1)
+        assert fr.status == orc.FIT_CONVERGED
+        assert fr.iters == 1, fr
+        assert fr.theta[0] == pytest.approx(c_hat, rel=1e-12)
+        plain = orc.fit(M, 2, n, [c0], (0, 1), weights=w, edm_tol=1e-22, hessian_init=0)
+        assert plain.theta[0] == pytest.approx(c_hat, rel=1e-8) and plain.iters > fr.iters
+
+
+def test_fisher_start_cuts_iterations_on_batch(orc):
+    """Same fits from the default starts with and without the Fisher start:
+    the minima agree and the Fisher start needs far fewer iterations."""
+    from oracle import mlp as omlp
+    c = datagen.batch_case(seed=31, B=48, lo_bins=256, hi_bins=8192)
+    M = orc.Model(2, 1, -1, 0.0, 1.0)
+    counts = c["counts"].astype(np.float64)
+    th0 = omlp.default_starts(counts, c["offsets"], c["ranges"])
+    r0 = orc.fit_many(M, 2, counts, c["offsets"], c["ranges"], th0, nthreads=8, hessian_init=0)
+    r1 = orc.fit_many(M, 2, counts, c["offsets"], c["ranges"], th0, nthreads=8, hessian_init=1)
+    both = (r0[2] == 0) & (r1[2] == 0)
+    assert both.mean() > 0.9
+    assert np.median(np.abs(r1[1] - r0[1])[both]) < 1e-6
+    assert r1[3].mean() < 0.5 * r0[3].mean(), (r1[3].mean(), r0[3].mean())
