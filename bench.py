@@ -48,14 +48,62 @@ BYTES_PER_BIN = 4  # one u32 count per bin
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "nll_grad_1e7_traffic.json")
 
 
+# Sources of the timed 1D kernel and of its launch (grid sizing in abi.cpp).
+KERNEL_SOURCES = ("device.hpp", "fastmath.hpp", "chunk.hpp", "nll_kernels.hpp", "nll1d_ng2.hip",
+                  "abi.cpp")
+HOT_KERNEL = {"fp64": "void hf::k_nll_1d<2, 3, 2, true, false>(hf::NllArgs)",
+              "fp32bin": "void hf::k_nll_1d<2, 3, 2, true, true>(hf::NllArgs)"}
+
+
 def kernel_source_hash():
     """Hash of the HIP sources the timed kernel is built from; HBM traffic
     measured with rocprofv3 counters is only reported for the same sources."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_06139_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode() + fh.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2203_06139_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
+
+
+def summarize_traffic(fetch_csv, write_csv, calib_mib, precision, objective, command):
+    """Turns two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, with --copy-calibration) into the traffic summary the bench
+    line reports: each counter's mean KiB per dispatch of the timed kernel,
+    scaled by true / counted bytes of the calibration copies."""
+    import csv
+
+    def read(path, counter):
+        kern, copies = [], []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                if r["Kernel_Name"] == HOT_KERNEL[precision]:
+                    kern.append(v)
+                elif r["Kernel_Name"] == "__amd_rocclr_copyBuffer":
+                    copies.append((int(r["Grid_Size"]), v))
+        if not kern or not copies:
+            raise SystemExit("%s: no %s rows for the kernel or the copies" % (path, counter))
+        big = max(g for g, _ in copies)
+        cal = [v for g, v in copies if g == big][-4:]
+        return sum(kern) / len(kern), sum(cal) / len(cal), len(kern)
+
+    true_kib = calib_mib * 1024.0
+    fk, fc, nf = read(fetch_csv, "FETCH_SIZE")
+    wk, wc, nw = read(write_csv, "WRITE_SIZE")
+    fscale, wscale = true_kib / fc, true_kib / wc
+    fetch_b, write_b = fk * 1024.0 * fscale, wk * 1024.0 * wscale
+    out = {"kernel": HOT_KERNEL[precision], "source_hash": kernel_source_hash(),
+           "commands": [command], "fetch_scale": fscale, "write_scale": wscale,
+           "fetch_kib_raw": fk, "write_kib_raw": wk, "dispatches": [nf, nw],
+           "per_launch_bytes": {"%s/%s" % (precision, objective): int(round(fetch_b + write_b))},
+           "fetch_bytes": int(round(fetch_b)), "write_bytes": int(round(write_b)),
+           "note": "FETCH_SIZE/WRITE_SIZE per dispatch x calibration scale"}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
 
 
 def measured_traffic(precision, objective):
@@ -122,13 +170,24 @@ def main():
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
                          "fit_batch; learned: plain vs learned-initialiser fits of that batch")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary from two rocprofv3 --pmc counter CSVs of a "
+                         "run with --copy-calibration (no GPU work)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after timing, copy a MIB-sized device buffer 4 times (a plain "
                          "copy of known size to scale HBM counters against)")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        # the profiled run is this script with the same flags
+        cmd = ("python bench.py --steps %d --warmup %d --no-cpu-baseline --copy-calibration %d "
+               "--precision %s --objective %s" % (args.steps, args.warmup, args.copy_calibration,
+                                                  args.precision, args.objective))
+        summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1],
+                          args.copy_calibration, args.precision, args.objective, cmd)
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU: the histogram objective is not sharded across GPUs "
-              "in this build (run with --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU: the histogram objective is not sharded across GPUs "
+              "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
