@@ -47,15 +47,38 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
   const uint16_t* b0p = g.B + static_cast<int64_t>(n0 + r) * g.ldb + kq;
   const uint16_t* b1p = b0p + 16 * g.ldb;
   f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
-  for (int k = 0; k < g.K; k += 32) {
-    const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(a0p + k);
-    const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(a1p + k);
-    const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(b0p + k);
-    const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(b1p + k);
-    c00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, c00, 0, 0, 0);
-    c01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, c01, 0, 0, 0);
-    c10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, c10, 0, 0, 0);
-    c11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, c11, 0, 0, 0);
+  // kStages K-steps of operands in flight: each step's loads are issued
+  // kStages steps before its MFMAs, so L2 latency overlaps the matrix work
+  // (a plain loop waits for every step's loads in turn).
+  constexpr int kStages = 4;
+  bf16x8 ra0[kStages], ra1[kStages], rb0[kStages], rb1[kStages];
+#pragma unroll
+  for (int s = 0; s < kStages; ++s) {
+    if (s * 32 < g.K) {
+      ra0[s] = *reinterpret_cast<const bf16x8*>(a0p + s * 32);
+      ra1[s] = *reinterpret_cast<const bf16x8*>(a1p + s * 32);
+      rb0[s] = *reinterpret_cast<const bf16x8*>(b0p + s * 32);
+      rb1[s] = *reinterpret_cast<const bf16x8*>(b1p + s * 32);
+    }
+  }
+  for (int k0 = 0; k0 < g.K; k0 += kStages * 32) {
+#pragma unroll
+    for (int s = 0; s < kStages; ++s) {
+      const int k = k0 + s * 32;
+      if (k < g.K) {
+        c00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra0[s], rb0[s], c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra0[s], rb1[s], c01, 0, 0, 0);
+        c10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra1[s], rb0[s], c10, 0, 0, 0);
+        c11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra1[s], rb1[s], c11, 0, 0, 0);
+        const int kn = k + kStages * 32;
+        if (kn < g.K) {
+          ra0[s] = *reinterpret_cast<const bf16x8*>(a0p + kn);
+          ra1[s] = *reinterpret_cast<const bf16x8*>(a1p + kn);
+          rb0[s] = *reinterpret_cast<const bf16x8*>(b0p + kn);
+          rb1[s] = *reinterpret_cast<const bf16x8*>(b1p + kn);
+        }
+      }
+    }
   }
   // lane holds D[4 (lane/16) + q][lane % 16] of each 16x16 tile
   const f32x4 acc[2][2] = {{c00, c01}, {c10, c11}};
@@ -125,24 +148,40 @@ hipError_t cast_nt(const float* w, int N, int K, uint16_t* wb, uint16_t* wt, hip
 }
 
 // loss = sum_{m, n<5} (y - t)^2 / (5B); dZ = bf16(2 (y - t) / (5B)), zero for
-// the padding columns; written [B][32] and transposed [32][B].  One block,
-// a fixed-order reduction.
-__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t,
-                                             int B, float* loss, uint16_t* dz, uint16_t* dzt) {
+// the padding columns; written [B][32] and transposed [32][B].  Each block
+// of 256 threads takes 8 rows and writes its FP64 partial sum of squares to
+// part[block]; k_mse_loss then sums the partials in block order.
+__global__ __launch_bounds__(256) void k_mse_grad(const float* __restrict__ y,
+                                                  const float* __restrict__ t, int B,
+                                                  uint16_t* dz, uint16_t* dzt,
+                                                  double* __restrict__ part) {
+  __shared__ double red[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;  // B * 32 is a multiple of 256
+  const int m = i / kMlpOutPad, n = i % kMlpOutPad;
+  const float scale = 2.0f / (5.0f * static_cast<float>(B));
+  float d = 0.0f;
+  double acc = 0.0;
+  if (n < kMlpOut) {
+    d = y[i] - t[m * kMlpOut + n];
+    acc = static_cast<double>(d) * d;
+  }
+  const uint16_t bv = f2bf(scale * d);
+  dz[i] = bv;
+  dzt[static_cast<int64_t>(n) * B + m] = bv;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_mse_loss(const double* __restrict__ part, int nparts, int B,
+                                                  float* loss) {
   __shared__ double red[256];
   double acc = 0.0;
-  const float scale = 2.0f / (5.0f * static_cast<float>(B));
-  for (int i = threadIdx.x; i < B * kMlpOutPad; i += 256) {
-    const int m = i / kMlpOutPad, n = i % kMlpOutPad;
-    float d = 0.0f;
-    if (n < kMlpOut) {
-      d = y[i] - t[m * kMlpOut + n];
-      acc += static_cast<double>(d) * d;
-    }
-    const uint16_t b = f2bf(scale * d);
-    dz[i] = b;
-    dzt[static_cast<int64_t>(n) * B + m] = b;
-  }
+  for (int q = threadIdx.x; q < nparts; q += 256) acc += part[q];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -153,22 +192,37 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const 
 }
 
 hipError_t mse(const float* y, const float* t, int B, float* loss, uint16_t* dz, uint16_t* dzt,
-               hipStream_t s) {
-  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, s, y, t, B, loss, dz, dzt);
+               double* part, hipStream_t s) {
+  const int nblk = B * kMlpOutPad / 256;
+  hipLaunchKernelGGL(k_mse_grad, dim3(nblk), dim3(256), 0, s, y, t, B, dz, dzt, part);
+  hipLaunchKernelGGL(k_mse_loss, dim3(1), dim3(256), 0, s, part, nblk, B, loss);
   return hipGetLastError();
 }
 
-// db[n] = sum_m dZ[m][n] (BF16 adjoints, FP32 sum in row order).
-__global__ void k_bias_grad(const uint16_t* __restrict__ dz, int B, int N, float* __restrict__ db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// db[n] = sum_m dZ[m][n] (BF16 adjoints, FP32 sums).  A block of 1024
+// threads takes 64 columns: 16 row groups each sum rows g, g+16, ... of one
+// column (coalesced across the 64 lanes), then the 16 group sums are added
+// in group order.
+__global__ __launch_bounds__(1024) void k_bias_grad(const uint16_t* __restrict__ dz, int B, int N,
+                                                    float* __restrict__ db) {
+  __shared__ float red[16][64];
+  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
   float acc = 0.0f;
-  for (int m = 0; m < B; ++m) acc += bf2f(dz[static_cast<int64_t>(m) * N + n]);
-  db[n] = acc;
+  if (n < N)
+    for (int m = grp; m < B; m += 16) acc += bf2f(dz[static_cast<int64_t>(m) * N + n]);
+  red[grp][c] = acc;
+  __syncthreads();
+  if (grp == 0 && n < N) {
+    float v = red[0][c];
+#pragma unroll
+    for (int q = 1; q < 16; ++q) v += red[q][c];
+    db[n] = v;
+  }
 }
 
 hipError_t bias_grad(const uint16_t* dz, int B, int N, float* db, hipStream_t s) {
-  hipLaunchKernelGGL(k_bias_grad, dim3((N + 255) / 256), dim3(256), 0, s, dz, B, N, db);
+  hipLaunchKernelGGL(k_bias_grad, dim3((N + 63) / 64), dim3(1024), 0, s, dz, B, N, db);
   return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ hipError_t gemm_nt(const GemmArgs& g, hipStream_t s);
 hipError_t cast_nt(const float* w, int N, int K, uint16_t* wb, uint16_t* wt, hipStream_t s);
 hipError_t cast_input(const float* x, int B, uint16_t* a, uint16_t* at, hipStream_t s);
 hipError_t mse(const float* y, const float* t, int B, float* loss, uint16_t* dz, uint16_t* dzt,
-               hipStream_t s);
+               double* part, hipStream_t s);
 hipError_t bias_grad(const uint16_t* dz, int B, int N, float* db, hipStream_t s);
 hipError_t adamw(float* p, float* m, float* v, const float* g, int64_t n, float lr, float wd,
                  int step, hipStream_t s);
@@ -76,6 +76,7 @@ struct MlpWorkspace {
   uint16_t* dzt[5]; // transposed
   uint16_t* wb[4];  // layer weights bf16 [out][in]
   uint16_t* wt[4];  // transposed [in][out]
+  double* loss_part;  // B*32/256 partial sums of the loss
 };
 
 int64_t mlp_workspace_bytes(int B);

@@ -36,6 +36,7 @@ MlpWorkspace carve(Carver& c, int B) {
     if (l >= 1) w.z[l] = c.take<float>(static_cast<int64_t>(B) * in);
   }
   w.y = c.take<float>(static_cast<int64_t>(B) * kMlpOutPad);
+  w.loss_part = c.take<double>(static_cast<int64_t>(B) * kMlpOutPad / 256);
   return w;
 }
 
@@ -111,7 +112,7 @@ hipError_t mlp_train_step(int B, float* params, float* m, float* v, int step, fl
                           hipStream_t s) {
   const MlpWorkspace w = mlp_carve(ws, B);
   HF_TRY(forward(B, params, x, w, true, w.y, s));
-  HF_TRY(mse(w.y, t, B, loss, w.dz[4], w.dzt[4], s));
+  HF_TRY(mse(w.y, t, B, loss, w.dz[4], w.dzt[4], w.loss_part, s));
   for (int l = 3; l >= 0; --l) {
     const int in = MlpLayout::kIn[l], out = MlpLayout::kOutDim[l];
     // dW_l[n][k] = sum_b dZ_l[b][n] A_{l-1}[b][k]
