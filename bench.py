@@ -404,7 +404,9 @@ def bench_fits(args, hf, datagen, np, torch, dev):
     t0 = hf.default_starts(counts, off, rg, m)
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
     from paper_2203_06139_amd.autotune import tune_fit
-    best, _ = tune_fit(counts, off, rg, m, t0, precision=prec, use_cache=False, log=log)
+    # tuned on the whole batch: its longest fits decide the wall time, and a
+    # random sample can miss them
+    best, _ = tune_fit(counts, off, rg, m, t0, precision=prec, sample=B, use_cache=False, log=log)
     log("autotuned: %s" % best)
     kw = dict(objective=hf.POISSON, precision=prec, polish_edm=best["polish_edm"])
     ref = hf.fit_batch(counts, off, rg, m, t0, objective=hf.POISSON, precision=hf.FP64)

@@ -212,15 +212,22 @@ int fit_batch(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t counts_
 
 
 /* Launch shape of fit_batch on this context (the autotuner's knobs):
- * wg_per_cu persistent workgroups per compute unit (1..16, default 2) and
+ * wg_per_cu persistent workgroups per compute unit (1..16, default 2);
  * cache_bins: histograms of u32 counts with at most this many bins are copied
  * once into LDS and every evaluation reads them there (0 = never; at most
- * hf_fit_max_cache_bins(), checked by fit_batch).  Host-only calls.        */
-int hf_fit_set_tuning(hf_ctx* ctx, int32_t wg_per_cu, int32_t cache_bins);
-int hf_fit_get_tuning(const hf_ctx* ctx, int32_t* wg_per_cu, int32_t* cache_bins);
-/* Largest cache_bins the fit kernel of this model and objective can hold in
- * LDS next to its own state (>= 0), or a negative hf_error.               */
-int hf_fit_max_cache_bins(hf_ctx* ctx, const hf_model* model, int32_t objective);
+ * hf_fit_max_cache_bins() for the block size, checked by fit_batch);
+ * block_size: threads per workgroup, each fit's bins shared among them (256
+ * = one wave per SIMD, default; or 512).  The results do not depend on the
+ * shape beyond summation order.  Host-only calls; HF_EINVAL for values out
+ * of range.                                                               */
+int hf_fit_set_tuning(hf_ctx* ctx, int32_t wg_per_cu, int32_t cache_bins, int32_t block_size);
+int hf_fit_get_tuning(const hf_ctx* ctx, int32_t* wg_per_cu, int32_t* cache_bins,
+                      int32_t* block_size);
+/* Largest cache_bins the fit kernel of this model and objective, with
+ * workgroups of block_size threads, can hold in LDS next to its own state
+ * (>= 0), or a negative hf_error.                                         */
+int hf_fit_max_cache_bins(hf_ctx* ctx, const hf_model* model, int32_t objective,
+                          int32_t block_size);
 
 /* ------------------------------------------------------------------------
  * Learned initialiser: a dense GELU network 256 -> 512 -> 512 -> 512 -> 5

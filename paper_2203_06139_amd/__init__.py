@@ -124,9 +124,10 @@ def load():
     L.hf_target_to_theta.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.hf_mlp_forward.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
     L.hf_mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp, vp, i64, vp]
-    L.hf_fit_set_tuning.argtypes = [vp, i32, i32]
-    L.hf_fit_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
-    L.hf_fit_max_cache_bins.argtypes = [vp, ctypes.POINTER(HfModel), i32]
+    L.hf_fit_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.hf_fit_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)]
+    L.hf_fit_max_cache_bins.argtypes = [vp, ctypes.POINTER(HfModel), i32, i32]
     for fn in (L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
                L.hf_target_to_theta, L.hf_mlp_forward, L.hf_mlp_train_step, L.hf_fit_set_tuning,
                L.hf_fit_get_tuning, L.hf_fit_max_cache_bins):
@@ -355,21 +356,23 @@ def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=PO
     return out
 
 
-def fit_set_tuning(wg_per_cu: int, cache_bins: int, device=None):
+def fit_set_tuning(wg_per_cu: int, cache_bins: int, block_size: int = 256, device=None):
+    """fit_batch launch shape of this device's context (see hf_fit_set_tuning)."""
     ctx = context(device)
-    _check(load().hf_fit_set_tuning(ctx, int(wg_per_cu), int(cache_bins)), ctx)
+    _check(load().hf_fit_set_tuning(ctx, int(wg_per_cu), int(cache_bins), int(block_size)), ctx)
 
 
 def fit_get_tuning(device=None):
+    """(wg_per_cu, cache_bins, block_size) of this device's context."""
     ctx = context(device)
-    w, c = ctypes.c_int32(), ctypes.c_int32()
-    _check(load().hf_fit_get_tuning(ctx, ctypes.byref(w), ctypes.byref(c)), ctx)
-    return w.value, c.value
+    w, c, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().hf_fit_get_tuning(ctx, ctypes.byref(w), ctypes.byref(c), ctypes.byref(b)), ctx)
+    return w.value, c.value, b.value
 
 
-def fit_max_cache_bins(model: Model, objective=POISSON, device=None) -> int:
+def fit_max_cache_bins(model: Model, objective=POISSON, block_size: int = 256, device=None) -> int:
     ctx = context(device)
-    rc = load().hf_fit_max_cache_bins(ctx, ctypes.byref(model.c()), objective)
+    rc = load().hf_fit_max_cache_bins(ctx, ctypes.byref(model.c()), objective, int(block_size))
     _check(rc if rc < 0 else 0, ctx)
     return rc
 

@@ -1,8 +1,9 @@
 """Autotuner of fit_batch's launch shape.
 
-Searches persistent workgroups per CU x the LDS count cache (in bins) x the
-FP32->FP64 polish threshold by timing fit_batch (HIP events) on a sample of
-the batch to be fitted, keeps the fastest configuration whose fits agree with
+Searches the workgroup size (256 or 512 threads) x persistent workgroups per
+CU x the LDS count cache (in bins) x the FP32->FP64 polish threshold by
+timing fit_batch (HIP events) on a sample of the batch to be fitted (the
+whole batch when `sample` is at least its size), keeps the fastest configuration whose fits agree with
 the FP64 fit of the same sample (|dNLL| < 1e-6 where both converge), applies
 it to the context, and caches it as JSON keyed by (GPU arch, CU count, model,
 objective, precision).  Cache file: $HF_AUTOTUNE_CACHE or
@@ -18,6 +19,7 @@ import torch
 
 from . import FP32_BIN, FP64, POISSON, Model, fit_batch, fit_max_cache_bins, fit_set_tuning
 
+BLOCKS = (256, 512)
 WG_PER_CU = (1, 2, 4, 8)
 POLISH = (1e-2, 1e-3, 1e-4)
 
@@ -59,7 +61,7 @@ def tune_fit(counts, offsets, ranges, model: Model, theta0, objective=POISSON, p
             known = json.load(f)
         if k in known:
             c = known[k]
-            fit_set_tuning(c["wg_per_cu"], c["cache_bins"])
+            fit_set_tuning(c["wg_per_cu"], c["cache_bins"], c.get("block_size", 256))
             return c, []
     B = offsets.numel() - 1
     g = torch.Generator().manual_seed(seed)
@@ -67,24 +69,28 @@ def tune_fit(counts, offsets, ranges, model: Model, theta0, objective=POISSON, p
     fs = subset(FitSet(counts, offsets.to(counts.device), ranges.to(counts.device)), idx.to(counts.device))
     th0 = theta0.to(counts.device)[idx.to(counts.device)].contiguous()
     ref = fit_batch(fs.counts, fs.offsets, fs.ranges, model, th0, objective=objective, precision=FP64)
-    cap = max(0, fit_max_cache_bins(model, objective))
-    caches = sorted({0, min(cap, 8192), min(cap, 16384), cap})
     polishes = POLISH if precision == FP32_BIN else (0.0,)
+    space = []
+    for blk in BLOCKS:
+        cap = max(0, fit_max_cache_bins(model, objective, blk))
+        caches = sorted({0, min(cap, 8192), min(cap, 16384), cap})
+        space += [(blk, wg, cb, pol) for wg, cb, pol in itertools.product(WG_PER_CU, caches, polishes)]
     results = []
-    for wg, cb, pol in itertools.product(WG_PER_CU, caches, polishes):
-        fit_set_tuning(wg, cb)
+    for blk, wg, cb, pol in space:
+        fit_set_tuning(wg, cb, blk)
         run = lambda: fit_batch(fs.counts, fs.offsets, fs.ranges, model, th0, objective=objective,
                                 precision=precision, polish_edm=pol)
         ms = _time(run)
         out = run()
         both = (out.status == 0) & (ref.status == 0)
         agree = bool(((out.nll - ref.nll).abs()[both] < 1e-6).all().item())
-        results.append(dict(wg_per_cu=wg, cache_bins=cb, polish_edm=pol, ms=ms, agree=agree))
+        results.append(dict(block_size=blk, wg_per_cu=wg, cache_bins=cb, polish_edm=pol, ms=ms,
+                            agree=agree))
         if log:
             log(results[-1])
     ok = [r for r in results if r["agree"]] or results
     best = min(ok, key=lambda r: r["ms"])
-    fit_set_tuning(best["wg_per_cu"], best["cache_bins"])
+    fit_set_tuning(best["wg_per_cu"], best["cache_bins"], best["block_size"])
     if use_cache:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         known = {}

@@ -342,7 +342,7 @@ HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
   if (o->hessian_init < 0 || o->hessian_init > 1 || o->reserved != 0)
     return fail(c, HF_EINVAL, "hessian_init must be 0 or 1 and reserved 0");
   if (c->fit.cache_bins > 0) {
-    const int cap = hf::fit_max_cache_bins(m->n_gauss, bkg_code(m), obj);
+    const int cap = hf::fit_max_cache_bins(m->n_gauss, bkg_code(m), obj, c->fit.block);
     if (c->fit.cache_bins > cap)
       return fail(c, HF_EINVAL, "LDS cache of %d bins exceeds the %d this fit kernel can hold",
                   c->fit.cache_bins, cap);
@@ -498,23 +498,29 @@ HF_EXPORT int hf_mlp_train_step(hf_ctx* c, int32_t batch, float* params, float* 
   return e == hipSuccess ? HF_OK : hip_fail(c, e, "mlp_train_step");
 }
 
-HF_EXPORT int hf_fit_set_tuning(hf_ctx* c, int32_t wg_per_cu, int32_t cache_bins) {
+HF_EXPORT int hf_fit_set_tuning(hf_ctx* c, int32_t wg_per_cu, int32_t cache_bins,
+                                int32_t block_size) {
   if (!c) return HF_EINVAL;
   if (wg_per_cu < 1 || wg_per_cu > 16) return fail(c, HF_EINVAL, "wg_per_cu outside 1..16");
   if (cache_bins < 0) return fail(c, HF_EINVAL, "cache_bins must be >= 0");
+  if (block_size != 256 && block_size != 512) return fail(c, HF_EINVAL, "block_size must be 256 or 512");
   c->fit.wg_per_cu = wg_per_cu;
   c->fit.cache_bins = cache_bins;
+  c->fit.block = block_size;
   return HF_OK;
 }
 
-HF_EXPORT int hf_fit_get_tuning(const hf_ctx* c, int32_t* wg_per_cu, int32_t* cache_bins) {
-  if (!c || !wg_per_cu || !cache_bins) return HF_EINVAL;
+HF_EXPORT int hf_fit_get_tuning(const hf_ctx* c, int32_t* wg_per_cu, int32_t* cache_bins,
+                                int32_t* block_size) {
+  if (!c || !wg_per_cu || !cache_bins || !block_size) return HF_EINVAL;
   *wg_per_cu = c->fit.wg_per_cu;
   *cache_bins = c->fit.cache_bins;
+  *block_size = c->fit.block;
   return HF_OK;
 }
 
-HF_EXPORT int hf_fit_max_cache_bins(hf_ctx* c, const hf_model* m, int32_t objective) {
+HF_EXPORT int hf_fit_max_cache_bins(hf_ctx* c, const hf_model* m, int32_t objective,
+                                    int32_t block_size) {
   if (!c) return HF_EINVAL;
   int rc = check_model(c, m);
   if (rc) return rc;
@@ -522,5 +528,6 @@ HF_EXPORT int hf_fit_max_cache_bins(hf_ctx* c, const hf_model* m, int32_t object
   if (objective < HF_NEYMAN || objective > HF_POISSON) return fail(c, HF_EINVAL, "objective unknown");
   rc = use_device(c);
   if (rc) return rc;
-  return hf::fit_max_cache_bins(m->n_gauss, bkg_code(m), objective);
+  if (block_size != 256 && block_size != 512) return fail(c, HF_EINVAL, "block_size must be 256 or 512");
+  return hf::fit_max_cache_bins(m->n_gauss, bkg_code(m), objective, block_size);
 }

@@ -4,7 +4,9 @@
 // Gaussians on a uniform grid.  With z_k = z_0 + k dz (dz = h/s) the factor
 // e_k = exp(-z_k^2/2) obeys e_{k+1} = e_k r_k and r_{k+1} = r_k D, with
 // r_0 = exp(-dz z_0 - dz^2/2) and D = exp(-dz^2): two exps per Gaussian per
-// chunk instead of one per bin.  After k steps the relative error is about
+// chunk instead of one per bin.  An exponential background exp(b0 + b1 t) is
+// a geometric sequence on the grid, E_{k+1} = E_k exp(b1 dt): one exp per
+// chunk.  After k steps the relative error is about
 // k^2/2 ulp.  The recurrence is used only when K |dz| <= 1: then an e_0 that
 // underflows (|z_0| > 38.6) implies every e_k in the chunk is below 1e-300,
 // so nothing that matters is lost; r_0's exponent is clamped to +-700 so
@@ -71,6 +73,11 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
     }
   }
   const double t0 = (xs - M.tshift) * M.ta;
+  double Eb = 0.0;  // exponential background at the current bin (recurrence)
+  if constexpr (RECUR && BKG == BKG_EXP) {
+    const double a0 = fma(M.c[1], t0, M.c[0]);
+    Eb = F32BIN ? exp_hw32(a0) : exp_fast(a0);
+  }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     // ---- forward sweep ----
@@ -91,8 +98,13 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
     const double t = fma(static_cast<double>(k), M.dt, t0);
     double E = 0.0;
     if constexpr (BKG == BKG_EXP) {
-      const double a = fma(M.c[1], t, M.c[0]);
-      E = F32BIN ? exp_hw32(a) : exp_fast(a);
+      if constexpr (RECUR) {
+        E = Eb;
+        Eb *= M.qE;
+      } else {
+        const double a = fma(M.c[1], t, M.c[0]);
+        E = F32BIN ? exp_hw32(a) : exp_fast(a);
+      }
       mu += E;
     } else if constexpr (S::NB > 0) {
       double b = M.c[S::NB - 1];

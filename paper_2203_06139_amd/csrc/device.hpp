@@ -46,10 +46,12 @@ struct Model1D {
   double c[S::NB > 0 ? S::NB : 1];
   double tshift, ta;  // t = (x - tshift) * ta; the subtraction first keeps t exact near 0
   // Uniform-grid constants for a chunk of consecutive bins of width h:
-  // dz = h/s per Gaussian, D = exp(-dz^2), dt = h/t_scale; `recur` is set
-  // when every Gaussian satisfies K |dz| <= 1 (see chunk_1d).
+  // dz = h/s per Gaussian, D = exp(-dz^2), dt = h/t_scale, qE = exp(b1 dt);
+  // `recur` is set when every Gaussian satisfies K |dz| <= 1 and the
+  // exponential background K |b1 dt| <= 1 (see chunk_1d).
   double dz[NG > 0 ? NG : 1], D[NG > 0 ? NG : 1];
   double dt;
+  double qE;  // exponential background: ratio exp(b1 dt) of neighbouring bins
   bool recur;
 
   __device__ __forceinline__ void init(const double* __restrict__ th, double t_shift,
@@ -75,6 +77,13 @@ struct Model1D {
       recur = recur && (K * fabs(dz[g]) <= 1.0);
     }
     dt = h * ta;
+    qE = 1.0;
+    if constexpr (BKG == BKG_EXP) {
+      // E_{k+1} = E_k exp(b1 dt): exact ratio on the grid; K |b1 dt| <= 1
+      // keeps q^K within [1/e, e], so the product loses no range
+      qE = exp(c[1] * dt);
+      recur = recur && (K * fabs(c[1] * dt) <= 1.0);
+    }
   }
 
   // Factor applied to accumulated adjoint component k (0 = NLL) at the end:
@@ -158,7 +167,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Sums v[0..NV) over the block; on return tot[k] holds the block total of
 // component k and *totf the OR of flags.  Ends with a barrier.
-template <int NV>
+template <int NV, int WAVES = kWaves>
 __device__ __forceinline__ void block_sum(double (&v)[NV], int flags, double* tot, int* totf,
                                           double (*red)[NV], int* redf) {
   const int lane = threadIdx.x & 63;
@@ -176,13 +185,13 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int flags, double* to
   if (threadIdx.x < NV) {
     double s = red[0][threadIdx.x];
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) s += red[w][threadIdx.x];
+    for (int w = 1; w < WAVES; ++w) s += red[w][threadIdx.x];
     tot[threadIdx.x] = s;
   }
   if (threadIdx.x == 0) {
     int o = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) o |= redf[w];
+    for (int w = 0; w < WAVES; ++w) o |= redf[w];
     *totf = o;
   }
   __syncthreads();

@@ -31,18 +31,18 @@ __global__ __launch_bounds__(kBlock) void k_rank_sizes(const int64_t* __restrict
   if (b < B) order[rank] = b;
 }
 
-FitLaunchFn pick_fit(int ng, int bkg, int obj) {
+FitLaunchFn pick_fit(int ng, int bkg, int obj, int blk) {
   switch (ng) {
     case 0:
-      return pick_fit_ng0(bkg, obj);
+      return pick_fit_ng0(bkg, obj, blk);
     case 1:
-      return pick_fit_ng1(bkg, obj);
+      return pick_fit_ng1(bkg, obj, blk);
     case 2:
-      return pick_fit_ng2(bkg, obj);
+      return pick_fit_ng2(bkg, obj, blk);
     case 3:
-      return pick_fit_ng3(bkg, obj);
+      return pick_fit_ng3(bkg, obj, blk);
     case 4:
-      return pick_fit_ng4(bkg, obj);
+      return pick_fit_ng4(bkg, obj, blk);
     default:
       return nullptr;
   }
@@ -65,15 +65,15 @@ void fit_scratch_free(FitScratch* s) {
   s->cap = 0;
 }
 
-int fit_max_cache_bins(int n_gauss, int bkg, int obj) {
-  FitLaunchFn fn = pick_fit(n_gauss, bkg, obj);
+int fit_max_cache_bins(int n_gauss, int bkg, int obj, int block) {
+  FitLaunchFn fn = pick_fit(n_gauss, bkg, obj, block);
   int m = 0;
   if (!fn || fn(FitArgs{}, 0, nullptr, &m) != hipSuccess) return 0;
   return m > 0 ? m : 0;
 }
 
 hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s, hipStream_t st) {
-  FitLaunchFn fn = pick_fit(n_gauss, bkg, a.obj);
+  FitLaunchFn fn = pick_fit(n_gauss, bkg, a.obj, s->block);
   if (!fn) return hipErrorNotSupported;
   a.cache_bins = s->cache_bins;
   a.sorted = a.B <= kMaxRankB ? 1 : 0;

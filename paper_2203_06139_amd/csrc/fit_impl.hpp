@@ -46,7 +46,7 @@ __device__ __forceinline__ double count_at(const void* base, int dtype, int64_t 
 // Entries of the expected Hessian accumulated per pass over the bins.
 constexpr int kFisherPass = 32;
 
-template <int NG, int BKG>
+template <int NG, int BKG, int BLK>
 struct FitShared {
   static constexpr int P = Shape1D<NG, BKG>::P;
   static constexpr int NV = P + 1;
@@ -55,12 +55,12 @@ struct FitShared {
   double H[P * P];   // row stride P; the leading nf x nf block is used
   double Lc[P * P];  // Fisher start: scaled F, its Cholesky factor, the inverse
   double tot[NV];
-  double red[kWaves][NV];
-  double fred[kWaves * kFisherPass];
+  double red[BLK / 64][NV];
+  double fred[(BLK / 64) * kFisherPass];
   double ftot[kFisherPass];
   double dmax;
-  int redf[kWaves];
-  int fredf[kWaves];
+  int redf[BLK / 64];
+  int fredf[BLK / 64];
   int totf, ftotf;
   int chol_ok;
   int fidx[P];
@@ -102,10 +102,10 @@ struct CountsSrc {
 // Objective and gradient of one histogram at sm.th, evaluated by the whole
 // workgroup with the chunked sweep (chunk_1d).  Leaves f in sm.tot[0]
 // (+inf on a domain error) and dL/dtheta_k in sm.tot[1 + k].
-template <int NG, int BKG, int OBJ, bool F32BIN>
-__device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG>& sm, const double2* lut,
+template <int NG, int BKG, int OBJ, bool F32BIN, int BLK>
+__device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
                         const CountsSrc& src, int64_t nb, double x0, double hx) {
-  constexpr int NV = FitShared<NG, BKG>::NV;
+  constexpr int NV = FitShared<NG, BKG, BLK>::NV;
   constexpr int K = kFitChunk;
   Model1D<NG, BKG> M;
   M.init(sm.th, a.t_shift, a.t_scale);
@@ -116,7 +116,7 @@ __device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
   int flags = 0;
   const int64_t nch = nb / K;
   const double w[K] = {1.0, 1.0, 1.0, 1.0};
-  for (int64_t c = threadIdx.x; c < nch; c += kBlock) {
+  for (int64_t c = threadIdx.x; c < nch; c += BLK) {
     const int64_t i0 = c * K;
     double n[K];
 #pragma unroll
@@ -128,14 +128,14 @@ __device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
     else
       chunk_1d<NG, BKG, OBJ, true, F32BIN, false>(M, lut, xs, n, w, acc, flags, l);
   }
-  for (int64_t i = nch * K + threadIdx.x; i < nb; i += kBlock) {
+  for (int64_t i = nch * K + threadIdx.x; i < nb; i += BLK) {
     const double n1[1] = {src.at(i)};
     const double w1[1] = {1.0};
     double l1[1];
     chunk_1d<NG, BKG, OBJ, true, F32BIN, false>(M, lut, fma(static_cast<double>(i), hx, x0), n1, w1,
                                                 acc, flags, l1);
   }
-  block_sum<NV>(acc, flags, sm.tot, &sm.totf, sm.red, sm.redf);
+  block_sum<NV, BLK / 64>(acc, flags, sm.tot, &sm.totf, sm.red, sm.redf);
   if (threadIdx.x >= 1 && threadIdx.x < NV) sm.tot[threadIdx.x] *= M.final_factor(threadIdx.x);
   if (threadIdx.x == 0 && (sm.totf & ST_DOMAIN)) sm.tot[0] = __builtin_inf();
   __syncthreads();
@@ -183,10 +183,10 @@ __device__ __forceinline__ double mu_partials(const Model1D<NG, BKG>& M, double 
 // n > 0 Neyman); bins whose c_i is not finite and positive are skipped.  The
 // upper triangle is accumulated kFisherPass entries per pass over the bins
 // and written symmetrically into sm.H.
-template <int NG, int BKG, int OBJ, int PASS>
-__device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG>& sm, const CountsSrc& src,
+template <int NG, int BKG, int OBJ, int PASS, int BLK>
+__device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const CountsSrc& src,
                             int64_t nb, double x0, double hx) {
-  constexpr int P = FitShared<NG, BKG>::P;
+  constexpr int P = FitShared<NG, BKG, BLK>::P;
   constexpr TriIndex<P> tri{};
   constexpr int E0 = PASS * kFisherPass;
   if constexpr (E0 < TriIndex<P>::N) {
@@ -196,7 +196,7 @@ __device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG>& sm, const Coun
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-    for (int64_t i = threadIdx.x; i < nb; i += kBlock) {
+    for (int64_t i = threadIdx.x; i < nb; i += BLK) {
       double v[P];
       const double mu = mu_partials(M, fma(static_cast<double>(i), hx, x0), v);
       double c;
@@ -211,13 +211,13 @@ __device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG>& sm, const Coun
         for (int q = 0; q < NQ; ++q) acc[q] = fma(c * v[tri.a[E0 + q]], v[tri.b[E0 + q]], acc[q]);
       }
     }
-    block_sum<NQ>(acc, 0, sm.ftot, &sm.ftotf, reinterpret_cast<double(*)[NQ]>(sm.fred), sm.fredf);
+    block_sum<NQ, BLK / 64>(acc, 0, sm.ftot, &sm.ftotf, reinterpret_cast<double(*)[NQ]>(sm.fred), sm.fredf);
     if (threadIdx.x < NQ) {
       const int r = tri.a[E0 + threadIdx.x], c = tri.b[E0 + threadIdx.x];
       sm.H[r * P + c] = sm.ftot[threadIdx.x];
       sm.H[c * P + r] = sm.ftot[threadIdx.x];
     }
-    fisher_pass<NG, BKG, OBJ, PASS + 1>(a, sm, src, nb, x0, hx);
+    fisher_pass<NG, BKG, OBJ, PASS + 1, BLK>(a, sm, src, nb, x0, hx);
   }
 }
 
@@ -227,12 +227,12 @@ __device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG>& sm, const Coun
 // inv(L) by forward substitution, H = inv(L)^T inv(L).  Falls back to the
 // identity when F_u is not safely positive definite or anything is not
 // finite.  Returns whether the inverse was taken.
-template <int NG, int BKG>
-__device__ bool fisher_start(FitShared<NG, BKG>& sm, int nf) {
-  constexpr int P = FitShared<NG, BKG>::P;
+template <int NG, int BKG, int BLK>
+__device__ bool fisher_start(FitShared<NG, BKG, BLK>& sm, int nf) {
+  constexpr int P = FitShared<NG, BKG, BLK>::P;
   const int tid = threadIdx.x;
   __syncthreads();
-  for (int t = tid; t < nf * nf; t += kBlock) {
+  for (int t = tid; t < nf * nf; t += BLK) {
     const int r = t / nf, c = t % nf;
     sm.Lc[r * P + c] = sm.sig[sm.fidx[r]] * sm.sig[sm.fidx[c]] * sm.H[sm.fidx[r] * P + sm.fidx[c]];
   }
@@ -270,7 +270,7 @@ __device__ bool fisher_start(FitShared<NG, BKG>& sm, int nf) {
       }
     }
     __syncthreads();
-    for (int t = tid; t < nf * nf; t += kBlock) {
+    for (int t = tid; t < nf * nf; t += BLK) {
       const int r = t / nf, c = t % nf;
       double v = 0.0;
       for (int k = (r > c ? r : c); k < nf; ++k) v += sm.H[k * P + r] * sm.H[k * P + c];
@@ -280,7 +280,7 @@ __device__ bool fisher_start(FitShared<NG, BKG>& sm, int nf) {
     __syncthreads();
   }
   const bool ok = sm.chol_ok != 0;
-  for (int t = tid; t < P * P; t += kBlock) {
+  for (int t = tid; t < P * P; t += BLK) {
     const int r = t / P, c = t % P;
     sm.H[t] = (ok && r < nf && c < nf) ? sm.Lc[r * P + c] : (r == c ? 1.0 : 0.0);
   }
@@ -289,11 +289,11 @@ __device__ bool fisher_start(FitShared<NG, BKG>& sm, int nf) {
 }
 
 // f(u) and g_u = sigma * dL/dtheta at theta = theta0 + sigma * u.
-template <int NG, int BKG, int OBJ>
-__device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG>& sm, const double2* lut,
+template <int NG, int BKG, int OBJ, int BLK>
+__device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
                                const CountsSrc& src, const double* uu, double* gout, bool f32,
                                int64_t nb, double x0, double hx) {
-  constexpr int P = FitShared<NG, BKG>::P;
+  constexpr int P = FitShared<NG, BKG, BLK>::P;
   const int tid = threadIdx.x;
   if (tid < P) sm.th[tid] = sm.th0[tid];
   __syncthreads();
@@ -303,9 +303,9 @@ __device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG>& sm, const d
   }
   __syncthreads();
   if (f32)
-    wg_eval<NG, BKG, OBJ, true>(a, sm, lut, src, nb, x0, hx);
+    wg_eval<NG, BKG, OBJ, true, BLK>(a, sm, lut, src, nb, x0, hx);
   else
-    wg_eval<NG, BKG, OBJ, false>(a, sm, lut, src, nb, x0, hx);
+    wg_eval<NG, BKG, OBJ, false, BLK>(a, sm, lut, src, nb, x0, hx);
   if (tid < sm.nf) {
     const int k = sm.fidx[tid];
     gout[tid] = sm.sig[k] * sm.tot[1 + k];
@@ -315,10 +315,10 @@ __device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG>& sm, const d
   return f;
 }
 
-template <int NG, int BKG, int OBJ>
-__device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2* lut,
+template <int NG, int BKG, int OBJ, int BLK>
+__device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
                         uint32_t* cache, int b) {
-  constexpr int P = FitShared<NG, BKG>::P;
+  constexpr int P = FitShared<NG, BKG, BLK>::P;
   constexpr int NB = Shape1D<NG, BKG>::NB;
   const int tid = threadIdx.x;
   const int64_t off = a.offsets[b];
@@ -340,7 +340,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
   CountsSrc src{nullptr, a.counts, a.dtype, off};
   if (a.dtype == DT_U32 && nb <= a.cache_bins) {  // keep the counts in LDS for all evaluations
     const uint32_t* g = static_cast<const uint32_t*>(a.counts) + off;
-    for (int64_t i = tid; i < nb; i += kBlock) cache[i] = g[i];
+    for (int64_t i = tid; i < nb; i += BLK) cache[i] = g[i];
     src.lds = cache;
   }
 
@@ -361,17 +361,17 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
     sm.nf = nf;
   }
   if (tid < P) sm.u[tid] = 0.0;
-  for (int t = tid; t < P * P; t += kBlock) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
+  for (int t = tid; t < P * P; t += BLK) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
   __syncthreads();
   const int nf = sm.nf;
   bool first = true;
   if (a.hessian_init == 1 && nf > 0) {
-    fisher_pass<NG, BKG, OBJ, 0>(a, sm, src, nb, x0, hx);
+    fisher_pass<NG, BKG, OBJ, 0, BLK>(a, sm, src, nb, x0, hx);
     first = !fisher_start(sm, nf);  // no first-update scaling after a Fisher start
   }
 
   bool f32 = a.f32 != 0;
-  double f = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.u, sm.g, f32, nb, x0, hx);
+  double f = wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.u, sm.g, f32, nb, x0, hx);
   int nev = 1, it = 0, status = FIT_MAXITER;
   if (!__builtin_isfinite(f)) {
     status = (f == __builtin_inf()) ? FIT_DOMAIN : FIT_NONFINITE;
@@ -391,7 +391,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
       if (f32 && a.polish_edm > 0.0 && edm < a.polish_edm) {
         // switch to FP64 bins for the rest of the fit
         f32 = false;
-        f = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.u, sm.g, false, nb, x0, hx);
+        f = wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.u, sm.g, false, nb, x0, hx);
         ++nev;
         if (!__builtin_isfinite(f)) {
           status = (f == __builtin_inf()) ? FIT_DOMAIN : FIT_NONFINITE;
@@ -407,7 +407,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
       for (int q = 0; q < nf; ++q) slope += sm.g[q] * sm.pv[q];
       if (!(slope < 0.0)) {  // H lost positive definiteness: restart from I
         __syncthreads();
-        for (int t = tid; t < P * P; t += kBlock) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
+        for (int t = tid; t < P * P; t += BLK) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
         if (tid < nf) sm.pv[tid] = -sm.g[tid];
         first = true;
         __syncthreads();
@@ -419,7 +419,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
       for (int ls = 0; ls < a.ls_max; ++ls) {
         if (tid < nf) sm.un[tid] = sm.u[tid] + alpha * sm.pv[tid];
         __syncthreads();
-        fn = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.un, sm.gn, f32, nb, x0, hx);
+        fn = wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.un, sm.gn, f32, nb, x0, hx);
         ++nev;
         if (__builtin_isfinite(fn) && fn <= f + 1e-4 * alpha * slope) {
           accepted = true;
@@ -446,7 +446,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
       if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
         if (first) {
           const double gam = sy / yy;
-          for (int t = tid; t < nf * nf; t += kBlock) sm.H[(t / nf) * P + t % nf] *= gam;
+          for (int t = tid; t < nf * nf; t += BLK) sm.H[(t / nf) * P + t % nf] *= gam;
           first = false;
           __syncthreads();
         }
@@ -460,7 +460,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
         for (int q = 0; q < nf; ++q) yHy += sm.yv[q] * sm.Hy[q];
         const double rho = 1.0 / sy;
         const double cc = rho * rho * yHy + rho;
-        for (int t = tid; t < nf * nf; t += kBlock) {
+        for (int t = tid; t < nf * nf; t += BLK) {
           const int r = t / nf, c = t % nf;
           sm.H[r * P + c] += -rho * (sm.Hy[r] * sm.sv[c] + sm.sv[r] * sm.Hy[c]) + cc * sm.sv[r] * sm.sv[c];
         }
@@ -474,7 +474,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
     }
   }
   double nll = f;
-  if (f32 && __builtin_isfinite(f)) nll = wg_objective<NG, BKG, OBJ>(a, sm, lut, src, sm.u, sm.gn, false, nb, x0, hx);
+  if (f32 && __builtin_isfinite(f)) nll = wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.u, sm.gn, false, nb, x0, hx);
   // final parameters, canonicalised
   if (tid < P) sm.th[tid] = sm.th0[tid];
   __syncthreads();
@@ -502,9 +502,9 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG>& sm, const double2*
   __syncthreads();
 }
 
-template <int NG, int BKG, int OBJ>
-__global__ __launch_bounds__(kBlock) void k_fit(FitArgs a) {
-  __shared__ FitShared<NG, BKG> sm;
+template <int NG, int BKG, int OBJ, int BLK>
+__global__ __launch_bounds__(BLK) void k_fit(FitArgs a) {
+  __shared__ FitShared<NG, BKG, BLK> sm;
   __shared__ double2 lut[OBJ == OBJ_POISSON ? kLogLut : 1];
   extern __shared__ uint32_t cache[];  // a.cache_bins entries
   const int tid = threadIdx.x;
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_fit(FitArgs a) {
     const int h = sm.h;
     __syncthreads();
     if (h >= a.B) break;
-    fit_one<NG, BKG, OBJ>(a, sm, lut, cache, a.sorted ? a.order[h] : h);
+    fit_one<NG, BKG, OBJ, BLK>(a, sm, lut, cache, a.sorted ? a.order[h] : h);
   }
   // the last workgroup to leave re-arms the queue for the next launch
   if (tid == 0) {
@@ -528,11 +528,11 @@ __global__ __launch_bounds__(kBlock) void k_fit(FitArgs a) {
   }
 }
 
-template <int NG, int BKG, int OBJ>
+template <int NG, int BKG, int OBJ, int BLK>
 hipError_t launch_fit_kernel(const FitArgs& a, int grid, hipStream_t s, int* max_cache) {
   if (grid <= 0) {  // report the largest dynamic LDS cache that still fits
     hipFuncAttributes attr;
-    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k_fit<NG, BKG, OBJ>));
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k_fit<NG, BKG, OBJ, BLK>));
     if (e != hipSuccess) return e;
     int dev = 0, lds = 0;
     e = hipGetDevice(&dev);
@@ -542,52 +542,61 @@ hipError_t launch_fit_kernel(const FitArgs& a, int grid, hipStream_t s, int* max
     *max_cache = static_cast<int>((lds - static_cast<int>(attr.sharedSizeBytes)) / 4);
     return hipSuccess;
   }
-  hipLaunchKernelGGL((k_fit<NG, BKG, OBJ>), dim3(grid), dim3(kBlock),
+  hipLaunchKernelGGL((k_fit<NG, BKG, OBJ, BLK>), dim3(grid), dim3(BLK),
                      sizeof(uint32_t) * static_cast<size_t>(a.cache_bins), s, a);
   return hipGetLastError();
 }
 
 using FitLaunchFn = hipError_t (*)(const FitArgs&, int, hipStream_t, int*);
 
+// Workgroup sizes the fitter is built for: 256 threads (one wave per SIMD)
+// or 512 (two), the second for batches whose longest fits set the time.
+template <int NG, int BKG, int OBJ>
+FitLaunchFn pick_fit_blk(int blk) {
+  if (blk == 256) return &launch_fit_kernel<NG, BKG, OBJ, 256>;
+  if (blk == 512) return &launch_fit_kernel<NG, BKG, OBJ, 512>;
+  return nullptr;
+}
+
 template <int NG, int BKG>
-FitLaunchFn pick_fit_obj(int obj) {
+FitLaunchFn pick_fit_obj(int obj, int blk) {
   switch (obj) {
     case OBJ_NEYMAN:
-      return &launch_fit_kernel<NG, BKG, OBJ_NEYMAN>;
+      return pick_fit_blk<NG, BKG, OBJ_NEYMAN>(blk);
     case OBJ_PEARSON:
-      return &launch_fit_kernel<NG, BKG, OBJ_PEARSON>;
+      return pick_fit_blk<NG, BKG, OBJ_PEARSON>(blk);
     case OBJ_POISSON:
-      return &launch_fit_kernel<NG, BKG, OBJ_POISSON>;
+      return pick_fit_blk<NG, BKG, OBJ_POISSON>(blk);
     default:
       return nullptr;
   }
 }
 
 template <int NG>
-FitLaunchFn pick_fit_ng(int bkg, int obj) {
+FitLaunchFn pick_fit_ng(int bkg, int obj, int blk) {
   switch (bkg) {
     case BKG_NONE:
       if constexpr (NG == 0) return nullptr;
-      else return pick_fit_obj<NG, BKG_NONE>(obj);
+      else return pick_fit_obj<NG, BKG_NONE>(obj, blk);
     case 0:
-      return pick_fit_obj<NG, 0>(obj);
+      return pick_fit_obj<NG, 0>(obj, blk);
     case 1:
-      return pick_fit_obj<NG, 1>(obj);
+      return pick_fit_obj<NG, 1>(obj, blk);
     case 2:
-      return pick_fit_obj<NG, 2>(obj);
+      return pick_fit_obj<NG, 2>(obj, blk);
     case 3:
-      return pick_fit_obj<NG, 3>(obj);
+      return pick_fit_obj<NG, 3>(obj, blk);
     case BKG_EXP:
-      return pick_fit_obj<NG, BKG_EXP>(obj);
+      return pick_fit_obj<NG, BKG_EXP>(obj, blk);
     default:
       return nullptr;
   }
 }
 
-FitLaunchFn pick_fit_ng0(int bkg, int obj);
-FitLaunchFn pick_fit_ng1(int bkg, int obj);
-FitLaunchFn pick_fit_ng2(int bkg, int obj);
-FitLaunchFn pick_fit_ng3(int bkg, int obj);
-FitLaunchFn pick_fit_ng4(int bkg, int obj);
+FitLaunchFn pick_fit_ng0(int bkg, int obj, int blk);
+FitLaunchFn pick_fit_ng1(int bkg, int obj, int blk);
+FitLaunchFn pick_fit_ng2(int bkg, int obj, int blk);
+FitLaunchFn pick_fit_ng3(int bkg, int obj, int blk);
+FitLaunchFn pick_fit_ng4(int bkg, int obj, int blk);
 
 }  // namespace hf

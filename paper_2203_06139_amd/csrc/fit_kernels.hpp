@@ -51,6 +51,7 @@ struct FitScratch {
   unsigned* counters = nullptr;
   int wg_per_cu = 2;   // persistent workgroups per CU
   int cache_bins = 0;  // histograms with at most this many u32 bins live in LDS
+  int block = 256;     // threads per workgroup (256 or 512)
 };
 
 hipError_t fit_scratch_init(FitScratch* s);
@@ -59,8 +60,8 @@ void fit_scratch_free(FitScratch* s);
 // Returns hipErrorNotSupported for a model without a fit kernel.
 hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s, hipStream_t st);
 
-// Largest LDS cache (in u32 bins) a fit workgroup can hold for this model
-// and objective next to its own state.
-int fit_max_cache_bins(int n_gauss, int bkg, int obj);
+// Largest LDS cache (in u32 bins) a fit workgroup of `block` threads can
+// hold for this model and objective next to its own state.
+int fit_max_cache_bins(int n_gauss, int bkg, int obj, int block);
 
 }  // namespace hf

@@ -2,5 +2,5 @@
 #include "fit_impl.hpp"
 
 namespace hf {
-FitLaunchFn pick_fit_ng0(int bkg, int obj) { return pick_fit_ng<0>(bkg, obj); }
+FitLaunchFn pick_fit_ng0(int bkg, int obj, int blk) { return pick_fit_ng<0>(bkg, obj, blk); }
 }  // namespace hf

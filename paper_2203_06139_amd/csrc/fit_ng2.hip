@@ -2,5 +2,5 @@
 #include "fit_impl.hpp"
 
 namespace hf {
-FitLaunchFn pick_fit_ng2(int bkg, int obj) { return pick_fit_ng<2>(bkg, obj); }
+FitLaunchFn pick_fit_ng2(int bkg, int obj, int blk) { return pick_fit_ng<2>(bkg, obj, blk); }
 }  // namespace hf

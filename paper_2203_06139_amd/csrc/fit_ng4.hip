@@ -2,5 +2,5 @@
 #include "fit_impl.hpp"
 
 namespace hf {
-FitLaunchFn pick_fit_ng4(int bkg, int obj) { return pick_fit_ng<4>(bkg, obj); }
+FitLaunchFn pick_fit_ng4(int bkg, int obj, int blk) { return pick_fit_ng<4>(bkg, obj, blk); }
 }  // namespace hf

@@ -166,3 +166,56 @@ def test_fit_batch_repeatable_and_graph_replay(hf):
         x = torch.randn(1000, device="cuda").sum()  # unrelated eager work
         torch.cuda.synchronize()
         del x
+
+
+def test_launch_shape_does_not_change_results(hf, orc):
+    """Every workgroup size, workgroups per CU and LDS cache setting fits the
+    same batch to the same minima (summation order aside), and matches the
+    oracle; out-of-range settings are refused without touching the state."""
+    c, th0 = _subset(48, seed=13)
+    m = hf.Model.from_spec(c["spec"])
+    rth, rnll, rst, _, _ = orc.fit_many(orc_model(orc, c["spec"]), 2, c["counts"], c["offsets"],
+                                        c["ranges"], th0, nthreads=8, hessian_init=1)
+    try:
+        for blk, wg in ((256, 1), (512, 1), (512, 4), (256, 8)):
+            cap = hf.fit_max_cache_bins(m, hf.POISSON, blk)
+            assert cap > 4096
+            for cb in (0, cap):
+                hf.fit_set_tuning(wg, cb, blk)
+                assert hf.fit_get_tuning() == (wg, cb, blk)
+                th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], c["offsets"],
+                                              c["ranges"], th0, objective=2)
+                both = (st == 0) & (rst == 0)
+                assert both.mean() > 0.9, (blk, wg, cb)
+                assert np.all(np.abs(nll - rnll)[both] < 1e-6), (blk, wg, cb)
+        for bad in ((0, 0, 256), (2, -1, 256), (2, 0, 384)):
+            with pytest.raises(hf.HistfitError):
+                hf.fit_set_tuning(*bad)
+        assert hf.fit_get_tuning() == (8, hf.fit_max_cache_bins(m, hf.POISSON, 256), 256)
+        hf.fit_set_tuning(2, hf.fit_max_cache_bins(m, hf.POISSON, 512) + 1, 512)
+        with pytest.raises(hf.HistfitError):
+            run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], th0)
+    finally:
+        hf.fit_set_tuning(2, 0, 256)
+
+
+def test_autotuner_picks_an_agreeing_shape(hf, tmp_path, monkeypatch):
+    import torch
+    from paper_2203_06139_amd.autotune import tune_fit
+    monkeypatch.setenv("HF_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    c, th0 = _subset(64, seed=17)
+    counts = to_dev_counts(c["counts"])
+    off = torch.as_tensor(c["offsets"]).cuda()
+    rg = torch.as_tensor(c["ranges"]).cuda()
+    m = hf.Model.from_spec(c["spec"])
+    try:
+        best, results = tune_fit(counts, off, rg, m, torch.as_tensor(th0).cuda(), sample=64)
+        assert best["agree"] and len(results) > 40
+        assert hf.fit_get_tuning() == (best["wg_per_cu"], best["cache_bins"], best["block_size"])
+        assert best["ms"] == min(r["ms"] for r in results if r["agree"])
+        hf.fit_set_tuning(2, 0, 256)
+        again, none = tune_fit(counts, off, rg, m, torch.as_tensor(th0).cuda(), sample=64)
+        assert none == [] and again == best  # from the cache file
+        assert hf.fit_get_tuning() == (best["wg_per_cu"], best["cache_bins"], best["block_size"])
+    finally:
+        hf.fit_set_tuning(2, 0, 256)

@@ -149,25 +149,31 @@ def test_training_reduces_loss(hf):
 
 @pytest.mark.slow
 def test_learned_init_beats_plain_starts(hf):
-    """Train on plain fits of 4096-bin histograms, then fit held-out
-    histograms from the learned start (with plain-start fallback): every fit
-    agrees with the plain fit within |dNLL| < 1e-6 where both converge, and
-    the learned start needs fewer iterations on average."""
+    """Train on 524,288 plain fits of 4096-bin histograms, then fit an uneven
+    4096-histogram batch (256..65536 bins, seeds disjoint from training) from
+    the learned start with plain-start fallback.  Where both converge, the
+    learned fit's NLL is within 1e-6 of the plain fit's or below it for more
+    than 99% of the histograms, it needs fewer iterations on average, and
+    the learned path (rebin, network, fits, refits) takes less time than the
+    plain one (default starts, fits)."""
     import torch
-    from paper_2203_06139_amd.learned_init import FitSet, LearnedInit, plain_fit
+    from paper_2203_06139_amd.learned_init import FitSet, LearnedInit, plain_fit, timed
     li = LearnedInit("cuda", seed=2, batch=1024)
-    kept = li.build_training_set(65536, seed=1000, log=lambda *a: None)
-    assert kept > 60000
-    li.train(epochs=12, lr=1e-3, log=lambda *a: None)
-    counts, off, rg, _ = datagen.batch_case_device(5, 4096, 4096, "cuda")
-    fs = FitSet(counts, off.cuda(), rg.cuda())
-    _, plain = plain_fit(fs)
-    learned, nfb = li.fit(fs)
-    torch.cuda.synchronize()
+    kept = li.build_training_set(524288, seed=1000, log=lambda *a: None)
+    assert kept > 500000
+    li.train(epochs=8, lr=1e-3, log=lambda *a: None)
+    c = datagen.batch_case(seed=7)
+    fs = FitSet(torch.from_numpy(c["counts"].view(np.int32)).cuda(),
+                torch.as_tensor(c["offsets"]).cuda(), torch.as_tensor(c["ranges"]).cuda())
+    plain_fit(fs)
+    li.fit(fs)  # warm-up of both paths
+    (_, plain), t_plain = timed(lambda: plain_fit(fs))
+    (learned, nfb), t_learned = timed(lambda: li.fit(fs))
     both = (plain.status == 0) & (learned.status == 0)
     assert both.float().mean().item() > 0.97
-    dn = (plain.nll - learned.nll).abs()[both]
-    assert (dn < 1e-6).float().mean().item() > 0.99, dn.max().item()
+    ok = (learned.nll - plain.nll)[both] < 1e-6
+    assert ok.float().mean().item() > 0.99, (learned.nll - plain.nll)[both].max().item()
     it_p = plain.iters.float().mean().item()
     it_l = learned.iters.float().mean().item()
     assert it_l < it_p, (it_l, it_p, nfb)
+    assert t_learned < t_plain, (t_learned, t_plain, nfb)
