@@ -240,7 +240,8 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   // 2D work items are 16-bin pieces of one row (a row's tail is a short piece)
   const int64_t items_bins =
       two_d ? ((a.nx + hf::kChunk2D - 1) / hf::kChunk2D) * hf::kChunk2D * a.ny : a.nx;
-  const int grid = objective_grid(c, items_bins, two_d ? hf::kChunk2D : hf::kChunk, per_cu);
+  const int grid = objective_grid(c, items_bins,
+                                  two_d ? hf::kChunk2D : hf::chunk_bins(m->n_gauss), per_cu);
   hipError_t e = fn(a, grid, stream, nullptr);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return HF_OK;

@@ -92,43 +92,51 @@ __device__ __forceinline__ void write_outputs(const NllArgs& a, const M& model, 
 // Bins per thread per step of the grid-stride loop (a multiple of 4: one
 // 16-byte load per 4 u32 counts), and the occupancy the register allocator
 // must leave room for (waves per SIMD).
-#ifndef HF_CHUNK
-#define HF_CHUNK 16
-#endif
-#ifndef HF_MIN_WAVES
-#define HF_MIN_WAVES 1
-#endif
-constexpr int kChunk = HF_CHUNK;
-constexpr int kMinWaves = HF_MIN_WAVES;
-static_assert(kChunk % 4 == 0, "chunk must be a multiple of 4 bins");
+// Bins per thread per step (K) and waves per SIMD (W) the 1D kernel is built
+// for.  Every bin of a chunk is interleaved with the others, so registers
+// grow with K: 16-bin chunks need ~300 VGPRs and run one wave per SIMD.
+// Measured on the 1e7-bin two-Gaussian workload: 12-bin chunks at two waves
+// per SIMD (252 VGPRs) are 7% faster while the histogram stays in the
+// last-level cache, but 15% slower when every call reads it from HBM (51.8
+// vs 59.7 us); the HBM-resident case is the one the kernel is built for.
+// K is a multiple of 4 (16-byte loads).
+template <int NG>
+struct Chunking {
+  static constexpr int K = 16;
+  static constexpr int W = 1;
+  static_assert(K % 4 == 0, "chunk must be a multiple of 4 bins");
+};
+constexpr int chunk_bins(int) { return 16; }
+constexpr int kMinWaves = 1;  // the 2D kernel: one wave per SIMD
 
 // Counts of one chunk as loaded: 4-byte dtypes travel as raw 16-byte vectors
 // so the next chunk can be fetched while the current one is computed.
+template <int K>
 struct ChunkRaw {
-  uint4 c[kChunk / 4];
-  float4 w[kChunk / 4];
+  uint4 c[K / 4];
+  float4 w[K / 4];
 };
 
-template <bool SPEC>
-__device__ __forceinline__ void load_raw(const NllArgs& a, int64_t i0, ChunkRaw& r) {
+template <bool SPEC, int K>
+__device__ __forceinline__ void load_raw(const NllArgs& a, int64_t i0, ChunkRaw<K>& r) {
   const uint4* cp = reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(a.counts) + i0);
 #pragma unroll
-  for (int q = 0; q < kChunk / 4; ++q) r.c[q] = cp[q];
+  for (int q = 0; q < K / 4; ++q) r.c[q] = cp[q];
   if (!SPEC && a.weights) {
     const float4* wp = reinterpret_cast<const float4*>(a.weights + i0);
 #pragma unroll
-    for (int q = 0; q < kChunk / 4; ++q) r.w[q] = wp[q];
+    for (int q = 0; q < K / 4; ++q) r.w[q] = wp[q];
   }
 }
 
 // SPEC: the counts are u32 and there are no weights (the common case, with
 // the conversions and weight products folded away); otherwise the dtype and
 // the weights are checked at run time.
-template <bool SPEC>
-__device__ __forceinline__ void unpack_raw(const NllArgs& a, const ChunkRaw& r, double (&n)[kChunk],
-                                           double (&w)[kChunk]) {
+template <bool SPEC, int K>
+__device__ __forceinline__ void unpack_raw(const NllArgs& a, const ChunkRaw<K>& r, double (&n)[K],
+                                           double (&w)[K]) {
 #pragma unroll
-  for (int q = 0; q < kChunk / 4; ++q) {
+  for (int q = 0; q < K / 4; ++q) {
     if (SPEC || a.dtype == DT_U32) {
       n[4 * q] = r.c[q].x;
       n[4 * q + 1] = r.c[q].y;
@@ -151,20 +159,20 @@ __device__ __forceinline__ void unpack_raw(const NllArgs& a, const ChunkRaw& r, 
   }
 }
 
-template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN, int NV>
+template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN, int K, int NV>
 __device__ __forceinline__ void chunk_step(const NllArgs& a, const Model1D<NG, BKG>& M,
-                                           const double2* lut, int64_t i0, const double (&n)[kChunk],
-                                           const double (&w)[kChunk], double seed,
+                                           const double2* lut, int64_t i0, const double (&n)[K],
+                                           const double (&w)[K], double seed,
                                            double (&acc)[NV], int& flags) {
   const double xs = fma(static_cast<double>(i0), a.hx, a.x0);
-  double l[kChunk];
+  double l[K];
   if (M.recur)
     chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, true>(M, lut, xs, n, w, acc, flags, l);
   else
     chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, false>(M, lut, xs, n, w, acc, flags, l);
   if (a.grad_w_out) {
 #pragma unroll
-    for (int q = 0; q < kChunk / 4; ++q) {
+    for (int q = 0; q < K / 4; ++q) {
       float4 o;
       o.x = static_cast<float>(seed * l[4 * q]);
       o.y = static_cast<float>(seed * l[4 * q + 1]);
@@ -178,43 +186,44 @@ __device__ __forceinline__ void chunk_step(const NllArgs& a, const Model1D<NG, B
 // Grid-stride loop over the full chunks of 4-byte counts, with the next chunk
 // loaded while the current one is computed.  `nxt` holds the thread's first
 // chunk (chunk tid), loaded by the caller when tid < nfull.
-template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN, bool SPEC, int NV>
+template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN, bool SPEC, int K, int NV>
 __device__ __forceinline__ void stream_chunks(const NllArgs& a, const Model1D<NG, BKG>& M,
                                               const double2* lut, int64_t nfull, int64_t tid,
-                                              int64_t stride, double seed, ChunkRaw nxt,
+                                              int64_t stride, double seed, ChunkRaw<K> nxt,
                                               double (&acc)[NV], int& flags) {
   for (int64_t c = tid; c < nfull; c += stride) {
-    const ChunkRaw cur = nxt;
-    if (c + stride < nfull) load_raw<SPEC>(a, (c + stride) * kChunk, nxt);
-    double n[kChunk], w[kChunk];
+    const ChunkRaw<K> cur = nxt;
+    if (c + stride < nfull) load_raw<SPEC>(a, (c + stride) * K, nxt);
+    double n[K], w[K];
     unpack_raw<SPEC>(a, cur, n, w);
-    chunk_step<NG, BKG, OBJ, GRAD, F32BIN>(a, M, lut, c * kChunk, n, w, seed, acc, flags);
+    chunk_step<NG, BKG, OBJ, GRAD, F32BIN>(a, M, lut, c * K, n, w, seed, acc, flags);
   }
 }
 
 template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN>
-__global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_1d(NllArgs a) {
+__global__ __launch_bounds__(kBlock, Chunking<NG>::W) void k_nll_1d(NllArgs a) {
+  constexpr int K = Chunking<NG>::K;
   using S = Shape1D<NG, BKG>;
   constexpr int NV = GRAD ? S::P + 1 : 1;
   const int64_t nb = a.nx;
-  const int64_t nfull = nb / kChunk;
+  const int64_t nfull = nb / K;
   const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   const bool spec = a.dtype == DT_U32 && !a.weights;
   // the first chunk's counts are requested before the log table, so the two
   // memory latencies overlap instead of adding up
-  ChunkRaw first;
+  ChunkRaw<K> first;
   if (a.dtype != DT_F64 && tid < nfull) {
     if (spec)
-      load_raw<true>(a, tid * kChunk, first);
+      load_raw<true>(a, tid * K, first);
     else
-      load_raw<false>(a, tid * kChunk, first);
+      load_raw<false>(a, tid * K, first);
   }
   __shared__ double2 lut[kLogLut];
   if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
   Model1D<NG, BKG> M;
   M.init(a.theta, a.t_shift, a.t_scale);
-  M.init_grid(a.hx, kChunk);
+  M.init_grid(a.hx, K);
   if constexpr (OBJ == OBJ_POISSON) __syncthreads();
   double acc[NV];
 #pragma unroll
@@ -230,20 +239,20 @@ __global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_1d(NllArgs a) {
                                                      flags);
   } else {
     for (int64_t c = tid; c < nfull; c += stride) {
-      const int64_t i0 = c * kChunk;
-      double n[kChunk], w[kChunk];
+      const int64_t i0 = c * K;
+      double n[K], w[K];
 #pragma unroll
-      for (int k = 0; k < kChunk; ++k) {
+      for (int k = 0; k < K; ++k) {
         n[k] = static_cast<const double*>(a.counts)[i0 + k];
         w[k] = a.weights ? static_cast<double>(a.weights[i0 + k]) : 1.0;
       }
       chunk_step<NG, BKG, OBJ, GRAD, F32BIN>(a, M, lut, i0, n, w, seed, acc, flags);
     }
   }
-  // ragged tail: fewer than kChunk bins, one per thread of the first threads
-  const int64_t tail = nb - nfull * kChunk;
+  // ragged tail: fewer than K bins, one per thread of the first threads
+  const int64_t tail = nb - nfull * K;
   if (tid < tail) {
-    const int64_t i = nfull * kChunk + tid;
+    const int64_t i = nfull * K + tid;
     const double n[1] = {load_count1(a, i)};
     const double w[1] = {a.weights ? static_cast<double>(a.weights[i]) : 1.0};
     double l[1];
