@@ -165,11 +165,13 @@ def main():
     ap.add_argument("--train-fits", type=int, default=1_000_000,
                     help="learned workload: plain fits the initialiser is trained on")
     ap.add_argument("--epochs", type=int, default=8, help="learned workload: training epochs")
-    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned"],
+    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned", "gradient"],
                     default="large1d",
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
-                         "fit_batch; learned: plain vs learned-initialiser fits of that batch")
+                         "fit_batch; learned: plain vs learned-initialiser fits of that batch; "
+                         "gradient: fits with the reverse-mode gradient vs central differences "
+                         "for 1..4 Gaussians")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc counter CSVs of a "
                          "run with --copy-calibration (no GPU work)")
@@ -205,6 +207,8 @@ def main():
         return bench_fits(args, hf, datagen, np, torch, dev)
     if args.workload == "learned":
         return bench_learned(args, hf, datagen, np, torch, dev)
+    if args.workload == "gradient":
+        return bench_gradient(args, hf, datagen, np, torch, dev)
     obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
 
@@ -387,6 +391,69 @@ def bench_hist2d(args, hf, datagen, np, torch, dev):
                                                "Poisson NLL + gradient + weight gradient",
                                       nbins=nb, precision=args.precision),
                           hbm_gbs=12 * nb / (ms * 1e-3) / 1e9)), flush=True)
+
+
+def bench_gradient(args, hf, datagen, np, torch, dev):
+    """The paper's comparison (sec. 4, Fig. 2b) on this framework: the same
+    fits with the gradient from the reverse-mode adjoint sweep and from
+    central differences of the objective (2P value sweeps per gradient), as
+    the number of parameters grows: K = 1..4 Gaussians on a linear
+    background (P = 3K + 2), 512 histograms of 10,000 bins each, FP64 bins,
+    one fit_batch launch per mode.  Plus the cost of one gradient of the
+    1e7-bin two-Gaussian + cubic histogram: nll_grad against 2P+1 nll_eval."""
+    rows = []
+    for K in (1, 2, 3, 4):
+        c = datagen.kgauss_batch_case(K)
+        counts = torch.from_numpy(c["counts"].view(np.int32)).to(dev)
+        off = torch.as_tensor(c["offsets"], device=dev)
+        rg = torch.as_tensor(c["ranges"], device=dev)
+        t0 = torch.as_tensor(c["theta0"], device=dev)
+        m = hf.Model.from_spec(c["spec"])
+        row = dict(gaussians=K, params=3 * K + 2, histograms=len(c["offsets"]) - 1)
+        ref = None
+        for name, mode in (("adjoint", hf.ADJOINT), ("central_diff", hf.FINITE_DIFF)):
+            out = hf.fit_batch(counts, off, rg, m, t0, objective=hf.POISSON, precision=hf.FP64,
+                               gradient=mode)
+            torch.cuda.synchronize()
+            ms = time_graph(torch, lambda k: hf.fit_batch(counts, off, rg, m, t0,
+                                                          objective=hf.POISSON, precision=hf.FP64,
+                                                          gradient=mode, out=out), 3)
+            if ref is None:
+                ref = (out.nll.clone(), out.status.clone())
+            ok = ((out.status == 0) & (ref[1] == 0) & ((out.nll - ref[0]).abs() < 1e-6)).sum().item()
+            row[name] = dict(ms=ms, fits_per_s=ok / (ms * 1e-3), agreeing=ok,
+                             mean_iters=float(out.iters.float().mean().item()),
+                             mean_evals=float(out.nevals.float().mean().item()))
+            log("K=%d %s: %.2f ms, %d agreeing, %.1f iterations, %.1f sweeps" % (
+                K, name, ms, ok, row[name]["mean_iters"], row[name]["mean_evals"]))
+        row["speedup"] = row["central_diff"]["ms"] / row["adjoint"]["ms"]
+        rows.append(row)
+    # one gradient of the 1e7-bin histogram: adjoint sweep vs 2P+1 value sweeps
+    case = datagen.large_fit_case(seed=2)
+    spec = case["spec"]
+    mL = hf.Model.from_spec(spec)
+    h = hf.make_hist(case["counts"], case["range"], device=dev)
+    th = torch.as_tensor(case["theta_eval"], dtype=torch.float64, device=dev)
+    nll = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(mL.nparams, dtype=torch.float64, device=dev)
+    for _ in range(4):
+        hf.nll_grad(h, mL, th, nll_out=nll, grad_out=g)
+        hf.nll_eval(h, mL, th, out=nll)
+    t_grad = time_graph(torch, lambda k: hf.nll_grad(h, mL, th, nll_out=nll, grad_out=g), 64)
+    t_eval = time_graph(torch, lambda k: hf.nll_eval(h, mL, th, out=nll), 64)
+    P = mL.nparams
+    per_call = dict(nbins=int(case["counts"].size), params=P, nll_grad_us=t_grad * 1e3,
+                    nll_eval_us=t_eval * 1e3, central_diff_gradient_us=(2 * P + 1) * t_eval * 1e3,
+                    speedup=(2 * P + 1) * t_eval / t_grad)
+    last = rows[-1]
+    print(json.dumps(dict(
+        metric="fits/s, reverse-mode vs central-difference gradient", value=last["adjoint"]["fits_per_s"],
+        unit="fits/s", n_gpus=1, steps=3, warmup=1, ms_per_step=last["adjoint"]["ms"],
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload="512 1D histograms of 10,000 bins, K Gaussians + linear background "
+                             "(K = 1..4), Poisson, FP64 bins, Fisher-started BFGS; value: adjoint "
+                             "gradient at K = 4"),
+        sweep=rows, per_call=per_call)), flush=True)
 
 
 def bench_fits(args, hf, datagen, np, torch, dev):

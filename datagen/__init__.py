@@ -227,6 +227,44 @@ def random_1d_case(spec, nbins, lo, hi, theta, seed, rel=0.02):
                 theta_eval=perturb(theta, rel, rng))
 
 
+def kgauss_batch_case(K, seed=6, B=512, nbins=10_000):
+    """B histograms of nbins bins on [0,1], each K Gaussians (A log-uniform
+    in [3e2, 3e3] counts/bin, means spread over [0.1, 0.9] with a U(-0.02,
+    0.02) jitter, s ~ U[0.01, 0.03]) on a linear background b0 + b1 x (b0 ~
+    U[20, 200] counts/bin, b1 ~ U[-0.5, 0.5] b0); starts: A and s scaled by
+    1 + 0.1 N(0,1), means moved by 0.5 s N(0,1), b0 by 1 + 0.05 N(0,1), b1
+    moved by 0.05 b0 N(0,1).  The workload of the gradient comparison (the
+    number of parameters grows with K, P = 3K + 2)."""
+    rng = np.random.Generator(np.random.PCG64(seed * 1000 + K))
+    spec = model_spec(GAUSS_POLY, K, 1, 0.0, 1.0)
+    P = 3 * K + 2
+    theta = np.empty((B, P))
+    th0 = np.empty((B, P))
+    counts = np.empty(B * nbins, dtype=np.uint32)
+    centres = np.linspace(0.1, 0.9, K) if K > 1 else np.array([0.5])
+    for b in range(B):
+        A = np.exp(rng.uniform(math.log(3e2), math.log(3e3), K))
+        m = centres + rng.uniform(-0.02, 0.02, K)
+        s = rng.uniform(0.01, 0.03, K)
+        b0 = rng.uniform(20.0, 200.0)
+        b1 = rng.uniform(-0.5, 0.5) * b0
+        t = np.empty(P)
+        t[0:3 * K:3], t[1:3 * K:3], t[2:3 * K:3] = A, m, s
+        t[3 * K], t[3 * K + 1] = b0, b1
+        theta[b] = t
+        counts[b * nbins:(b + 1) * nbins] = poisson_counts(intensity_1d(spec, t, nbins, 0.0, 1.0), rng)
+        z = t.copy()
+        z[0:3 * K:3] *= 1 + 0.1 * rng.standard_normal(K)
+        z[1:3 * K:3] += 0.5 * s * rng.standard_normal(K)
+        z[2:3 * K:3] *= 1 + 0.1 * rng.standard_normal(K)
+        z[3 * K] *= 1 + 0.05 * rng.standard_normal()
+        z[3 * K + 1] += 0.05 * b0 * rng.standard_normal()
+        th0[b] = z
+    offsets = np.arange(B + 1, dtype=np.int64) * nbins
+    ranges = np.tile(np.array([0.0, 1.0]), (B, 1))
+    return dict(spec=spec, counts=counts, offsets=offsets, ranges=ranges, theta_true=theta, theta0=th0)
+
+
 def batch_case_device(seed, B, nbins=4096, device="cuda"):
     """The batched-fit distribution (see batch_case) with a fixed bin count,
     generated on a torch device: parameters from a seeded CPU generator,

@@ -180,7 +180,13 @@ typedef struct {
   double polish_edm;    /* HF_FP32_BIN: switch to FP64 bins once EDM is
                            below this (<= 0: never switch)                */
   int32_t hessian_init; /* 0: identity; 1: inverse expected Hessian       */
-  int32_t reserved;     /* must be 0                                      */
+  int32_t gradient;     /* 0: reverse-mode adjoint sweep (value and
+                           gradient in one pass); 1: central differences
+                           of the value, g_q = (L(u + h e_q) - L(u - h e_q))
+                           / 2h in the scaled coordinates, h = 1e-4
+                           max(1, |u_q|): 2 nf value sweeps per gradient,
+                           taken only at accepted points (the line search
+                           needs values only).  1 requires HF_FP64.      */
 } hf_fit_opts;
 
 /* Per-fit status codes written to status[b] by fit_batch.                */

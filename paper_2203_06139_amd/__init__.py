@@ -28,6 +28,7 @@ U32, F32, F64 = 0, 1, 2
 ST_DOMAIN, ST_NONFINITE = 1, 2
 FIT_CONVERGED, FIT_MAXITER, FIT_LSFAIL, FIT_NONFINITE, FIT_DOMAIN, FIT_BADHIST = range(6)
 IDENTITY, FISHER = 0, 1  # fit_batch hessian_init
+ADJOINT, FINITE_DIFF = 0, 1  # fit_batch gradient
 
 
 class HfModel(ctypes.Structure):
@@ -48,7 +49,7 @@ class HfFitOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("ls_max", ctypes.c_int32),
                 ("fixed_iters", ctypes.c_int32), ("free_mask", ctypes.c_uint32),
                 ("edm_tol", ctypes.c_double), ("polish_edm", ctypes.c_double),
-                ("hessian_init", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("hessian_init", ctypes.c_int32), ("gradient", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -318,10 +319,12 @@ class FitBatchResult:
 
 def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=POISSON,
               precision=FP64, max_iter=500, ls_max=30, fixed_iters=False, free_mask=0,
-              edm_tol=1e-10, polish_edm=0.0, hessian_init=FISHER,
+              edm_tol=1e-10, polish_edm=0.0, hessian_init=FISHER, gradient=ADJOINT,
               out: FitBatchResult | None = None):
     """Fit B histograms laid end to end in counts_concat; device tensors out.
-    hessian_init: IDENTITY or FISHER (inverse expected Hessian at theta0)."""
+    hessian_init: IDENTITY or FISHER (inverse expected Hessian at theta0);
+    gradient: ADJOINT (reverse-mode sweep) or FINITE_DIFF (central
+    differences of the objective, FP64 only)."""
     import torch
     c = counts_concat
     dev = c.device
@@ -347,7 +350,7 @@ def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=PO
                              torch.empty(B, dtype=torch.int32, device=dev),
                              torch.empty(B, dtype=torch.int32, device=dev))
     opts = HfFitOpts(max_iter, ls_max, 1 if fixed_iters else 0, free_mask, edm_tol, polish_edm,
-                     int(hessian_init), 0)
+                     int(hessian_init), int(gradient))
     rc = load().fit_batch(ctx, B, _ptr(c), _dtype_code(c), _ptr(off), _ptr(rg),
                           ctypes.byref(model.c()), objective, precision, _ptr(th0),
                           ctypes.byref(opts), _ptr(out.theta), _ptr(out.nll), _ptr(out.status),

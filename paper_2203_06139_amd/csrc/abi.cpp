@@ -340,8 +340,12 @@ HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
     return fail(c, HF_EINVAL, "precision %d unknown", prec);
   if (o->max_iter < 1 || o->ls_max < 1 || o->ls_max > 60 || !(o->edm_tol >= 0.0))
     return fail(c, HF_EINVAL, "fit options out of range");
-  if (o->hessian_init < 0 || o->hessian_init > 1 || o->reserved != 0)
-    return fail(c, HF_EINVAL, "hessian_init must be 0 or 1 and reserved 0");
+  if (o->hessian_init < 0 || o->hessian_init > 1)
+    return fail(c, HF_EINVAL, "hessian_init must be 0 or 1");
+  if (o->gradient < 0 || o->gradient > 1)
+    return fail(c, HF_EINVAL, "gradient must be 0 (adjoint) or 1 (central differences)");
+  if (o->gradient == 1 && prec != HF_FP64)
+    return fail(c, HF_EINVAL, "central-difference gradients need FP64 bins");
   if (c->fit.cache_bins > 0) {
     const int cap = hf::fit_max_cache_bins(m->n_gauss, bkg_code(m), obj, c->fit.block);
     if (c->fit.cache_bins > cap)
@@ -372,6 +376,7 @@ HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
   a.edm_tol = o->edm_tol;
   a.polish_edm = o->polish_edm;
   a.hessian_init = o->hessian_init;
+  a.fd_grad = o->gradient;
   a.t_shift = m->t_shift;
   a.t_scale = m->t_scale;
   a.P = nparams(m);

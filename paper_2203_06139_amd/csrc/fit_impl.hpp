@@ -51,7 +51,7 @@ struct FitShared {
   static constexpr int P = Shape1D<NG, BKG>::P;
   static constexpr int NV = P + 1;
   double th[P], th0[P], sig[P];
-  double u[P], g[P], un[P], gn[P], pv[P], tmp[P], sv[P], yv[P], Hy[P];
+  double u[P], g[P], un[P], gn[P], pv[P], tmp[P], sv[P], yv[P], Hy[P], up[P];
   double H[P * P];   // row stride P; the leading nf x nf block is used
   double Lc[P * P];  // Fisher start: scaled F, its Cholesky factor, the inverse
   double tot[NV];
@@ -99,13 +99,14 @@ struct CountsSrc {
   }
 };
 
-// Objective and gradient of one histogram at sm.th, evaluated by the whole
-// workgroup with the chunked sweep (chunk_1d).  Leaves f in sm.tot[0]
-// (+inf on a domain error) and dL/dtheta_k in sm.tot[1 + k].
-template <int NG, int BKG, int OBJ, bool F32BIN, int BLK>
+// Objective (and with GRAD its gradient) of one histogram at sm.th,
+// evaluated by the whole workgroup with the chunked sweep (chunk_1d).
+// Leaves f in sm.tot[0] (+inf on a domain error) and dL/dtheta_k in
+// sm.tot[1 + k].
+template <int NG, int BKG, int OBJ, bool F32BIN, bool GRAD, int BLK>
 __device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
                         const CountsSrc& src, int64_t nb, double x0, double hx) {
-  constexpr int NV = FitShared<NG, BKG, BLK>::NV;
+  constexpr int NV = GRAD ? FitShared<NG, BKG, BLK>::NV : 1;
   constexpr int K = kFitChunk;
   Model1D<NG, BKG> M;
   M.init(sm.th, a.t_shift, a.t_scale);
@@ -124,18 +125,19 @@ __device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
     double l[K];
     const double xs = fma(static_cast<double>(i0), hx, x0);
     if (M.recur)
-      chunk_1d<NG, BKG, OBJ, true, F32BIN, true>(M, lut, xs, n, w, acc, flags, l);
+      chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, true>(M, lut, xs, n, w, acc, flags, l);
     else
-      chunk_1d<NG, BKG, OBJ, true, F32BIN, false>(M, lut, xs, n, w, acc, flags, l);
+      chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, false>(M, lut, xs, n, w, acc, flags, l);
   }
   for (int64_t i = nch * K + threadIdx.x; i < nb; i += BLK) {
     const double n1[1] = {src.at(i)};
     const double w1[1] = {1.0};
     double l1[1];
-    chunk_1d<NG, BKG, OBJ, true, F32BIN, false>(M, lut, fma(static_cast<double>(i), hx, x0), n1, w1,
+    chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, false>(M, lut, fma(static_cast<double>(i), hx, x0), n1, w1,
                                                 acc, flags, l1);
   }
-  block_sum<NV, BLK / 64>(acc, flags, sm.tot, &sm.totf, sm.red, sm.redf);
+  block_sum<NV, BLK / 64>(acc, flags, sm.tot, &sm.totf, reinterpret_cast<double(*)[NV]>(sm.red),
+                          sm.redf);
   if (threadIdx.x >= 1 && threadIdx.x < NV) sm.tot[threadIdx.x] *= M.final_factor(threadIdx.x);
   if (threadIdx.x == 0 && (sm.totf & ST_DOMAIN)) sm.tot[0] = __builtin_inf();
   __syncthreads();
@@ -303,9 +305,9 @@ __device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, co
   }
   __syncthreads();
   if (f32)
-    wg_eval<NG, BKG, OBJ, true, BLK>(a, sm, lut, src, nb, x0, hx);
+    wg_eval<NG, BKG, OBJ, true, true, BLK>(a, sm, lut, src, nb, x0, hx);
   else
-    wg_eval<NG, BKG, OBJ, false, BLK>(a, sm, lut, src, nb, x0, hx);
+    wg_eval<NG, BKG, OBJ, false, true, BLK>(a, sm, lut, src, nb, x0, hx);
   if (tid < sm.nf) {
     const int k = sm.fidx[tid];
     gout[tid] = sm.sig[k] * sm.tot[1 + k];
@@ -313,6 +315,50 @@ __device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, co
   const double f = sm.tot[0];
   __syncthreads();
   return f;
+}
+
+// f(u) alone (FP64 bins): the value the finite-difference gradient and its
+// line search need.
+template <int NG, int BKG, int OBJ, int BLK>
+__device__ double wg_value(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
+                           const CountsSrc& src, const double* uu, int64_t nb, double x0,
+                           double hx) {
+  constexpr int P = FitShared<NG, BKG, BLK>::P;
+  const int tid = threadIdx.x;
+  if (tid < P) sm.th[tid] = sm.th0[tid];
+  __syncthreads();
+  if (tid < sm.nf) {
+    const int k = sm.fidx[tid];
+    sm.th[k] = fma(sm.sig[k], uu[tid], sm.th0[k]);
+  }
+  __syncthreads();
+  wg_eval<NG, BKG, OBJ, false, false, BLK>(a, sm, lut, src, nb, x0, hx);
+  const double f = sm.tot[0];
+  __syncthreads();
+  return f;
+}
+
+// Central differences in the scaled coordinates, the gradient a fitter
+// without derivatives of the model uses: g_q = (f(u + h e_q) - f(u - h e_q))
+// / (2h) with h = kFdStep max(1, |u_q|), 2 nf objective sweeps.
+constexpr double kFdStep = 1e-4;
+
+template <int NG, int BKG, int OBJ, int BLK>
+__device__ void wg_fd_grad(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
+                           const CountsSrc& src, const double* uu, double* gout, int64_t nb,
+                           double x0, double hx) {
+  const int tid = threadIdx.x;
+  const int nf = sm.nf;
+  for (int q = 0; q < nf; ++q) {
+    const double h = kFdStep * fmax(1.0, fabs(uu[q]));
+    const double up = uu[q] + h, um = uu[q] - h;
+    if (tid < nf) sm.up[tid] = (tid == q) ? up : uu[tid];
+    const double fp = wg_value<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.up, nb, x0, hx);
+    if (tid < nf) sm.up[tid] = (tid == q) ? um : uu[tid];
+    const double fm = wg_value<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.up, nb, x0, hx);
+    if (tid == 0) gout[q] = (fp - fm) / (up - um);
+  }
+  __syncthreads();
 }
 
 template <int NG, int BKG, int OBJ, int BLK>
@@ -371,8 +417,18 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
   }
 
   bool f32 = a.f32 != 0;
-  double f = wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.u, sm.g, f32, nb, x0, hx);
+  const bool fd = a.fd_grad != 0;  // central differences (FP64 bins only)
+  double f;
   int nev = 1, it = 0, status = FIT_MAXITER;
+  if (fd) {
+    f = wg_value<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.u, nb, x0, hx);
+    if (__builtin_isfinite(f)) {
+      wg_fd_grad<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.u, sm.g, nb, x0, hx);
+      nev += 2 * nf;
+    }
+  } else {
+    f = wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.u, sm.g, f32, nb, x0, hx);
+  }
   if (!__builtin_isfinite(f)) {
     status = (f == __builtin_inf()) ? FIT_DOMAIN : FIT_NONFINITE;
   } else {
@@ -419,7 +475,8 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
       for (int ls = 0; ls < a.ls_max; ++ls) {
         if (tid < nf) sm.un[tid] = sm.u[tid] + alpha * sm.pv[tid];
         __syncthreads();
-        fn = wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.un, sm.gn, f32, nb, x0, hx);
+        fn = fd ? wg_value<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.un, nb, x0, hx)
+                : wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.un, sm.gn, f32, nb, x0, hx);
         ++nev;
         if (__builtin_isfinite(fn) && fn <= f + 1e-4 * alpha * slope) {
           accepted = true;
@@ -432,6 +489,10 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
         break;
       }
       ++it;
+      if (fd) {  // the gradient only at the accepted point
+        wg_fd_grad<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.un, sm.gn, nb, x0, hx);
+        nev += 2 * nf;
+      }
       if (tid < nf) {
         sm.sv[tid] = sm.un[tid] - sm.u[tid];
         sm.yv[tid] = sm.gn[tid] - sm.g[tid];

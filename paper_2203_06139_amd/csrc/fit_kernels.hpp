@@ -41,6 +41,7 @@ struct FitArgs {
   const double2* log_lut;  // kLogLut entries (Poisson)
   int32_t cache_bins;      // LDS cache capacity (u32 counts); 0 = no cache
   int32_t hessian_init;    // 0 identity, 1 inverse expected Hessian at theta0
+  int32_t fd_grad;         // 1: central-difference gradient (FP64 bins)
 };
 
 // Device scratch of the fitter, owned by the context.  `order` grows with B;

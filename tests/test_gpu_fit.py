@@ -219,3 +219,28 @@ def test_autotuner_picks_an_agreeing_shape(hf, tmp_path, monkeypatch):
         assert hf.fit_get_tuning() == (best["wg_per_cu"], best["cache_bins"], best["block_size"])
     finally:
         hf.fit_set_tuning(2, 0, 256)
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_finite_difference_fits_reach_the_adjoint_minima(hf, orc, K):
+    """Central-difference gradients (the comparison the paper draws) lead the
+    same fitter to the oracle's minima; every gradient costs 2 nf value
+    sweeps, and FP32 bins are refused for it."""
+    c = datagen.kgauss_batch_case(K, seed=9, B=24, nbins=4000)
+    P = 3 * K + 2
+    kw = dict(objective=2, precision=0)
+    ad = run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], c["theta0"],
+                 gradient=hf.ADJOINT, **kw)
+    fd = run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], c["theta0"],
+                 gradient=hf.FINITE_DIFF, **kw)
+    rth, rnll, rst, _, _ = orc.fit_many(orc_model(orc, c["spec"]), 2, c["counts"], c["offsets"],
+                                        c["ranges"], c["theta0"], nthreads=8, hessian_init=1)
+    both = (ad[2] == 0) & (fd[2] == 0) & (rst == 0)
+    assert both.mean() > 0.9, (ad[2], fd[2], rst)
+    assert np.all(np.abs(ad[1] - rnll)[both] < 1e-6)
+    assert np.all(np.abs(fd[1] - rnll)[both] < 1e-6), np.abs(fd[1] - rnll)[both].max()
+    # value sweeps: 1 + 2P at the start, then per iteration the trials + 2P
+    assert np.all(fd[4] >= (1 + 2 * P) + fd[3] * (1 + 2 * P))
+    with pytest.raises(hf.HistfitError):
+        run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], c["theta0"],
+                gradient=hf.FINITE_DIFF, objective=2, precision=1)
