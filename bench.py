@@ -393,6 +393,33 @@ def bench_hist2d(args, hf, datagen, np, torch, dev):
                           hbm_gbs=12 * nb / (ms * 1e-3) / 1e9)), flush=True)
 
 
+def fits_cpu_baseline(c, theta0, np, seconds=10.0):
+    """The oracle's fitter (FP64 bins, Fisher start, same starts) over host
+    threads, one histogram per thread at a time, on the first histograms of
+    the batch until about `seconds` have passed; fits/s over that sample."""
+    import oracle
+    spec = c["spec"]
+    m = oracle.Model(spec["kind"], spec["n_gauss"], spec["poly_degree"], spec["t_shift"],
+                     spec["t_scale"])
+    cores = cpu_cores()
+    off = c["offsets"]
+    counts = c["counts"].astype(np.float64)
+    done, t0 = 0, time.perf_counter()
+    B = len(off) - 1
+    while done < B and time.perf_counter() - t0 < seconds:
+        n = min(4 * cores, B - done)
+        sub = off[done:done + n + 1] - off[done]
+        oracle.fit_many(m, oracle.POISSON, counts[off[done]:off[done + n]], sub,
+                        c["ranges"][done:done + n], theta0[done:done + n], nthreads=cores,
+                        hessian_init=1)
+        done += n
+    dt = time.perf_counter() - t0
+    bins = int(off[done] - off[0])
+    return dict(value=done / dt, unit="fits/s", cores=cores, kind="oracle",
+                sample="the first %d of the %d histograms (%d bins), %.1f s, %d threads, FP64 "
+                       "bins" % (done, B, bins, dt, cores))
+
+
 def bench_gradient(args, hf, datagen, np, torch, dev):
     """The paper's comparison (sec. 4, Fig. 2b) on this framework: the same
     fits with the gradient from the reverse-mode adjoint sweep and from
@@ -482,6 +509,9 @@ def bench_fits(args, hf, datagen, np, torch, dev):
     steps = max(1, min(args.steps, 5))
     ms = time_graph(torch, lambda k: hf.fit_batch(counts, off, rg, m, t0, out=out, **kw), steps)
     ok = ((out.status == 0) & (ref.status == 0) & ((out.nll - ref.nll).abs() < 1e-6)).sum().item()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = fits_cpu_baseline(c, t0.cpu().numpy(), np)
     print(json.dumps(dict(metric="fits/s at |dNLL|<1e-6", value=ok / (ms * 1e-3), unit="fits/s",
                           n_gpus=1, steps=steps, warmup=1, ms_per_step=ms, higher_is_better=True,
                           scaling="weak", vs_baseline=None,
@@ -493,7 +523,8 @@ def bench_fits(args, hf, datagen, np, torch, dev):
                                       total_bins=int(c["offsets"][-1]), agreeing=ok,
                                       mean_iters=float(out.iters.float().mean().item()),
                                       mean_evals=float(out.nevals.float().mean().item()),
-                                      precision=args.precision, tuning=best))), flush=True)
+                                      precision=args.precision, tuning=best),
+                          cpu_baseline=cpu)), flush=True)
 
 
 def bench_learned(args, hf, datagen, np, torch, dev):
