@@ -73,6 +73,25 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
     }
   }
   const double t0 = (xs - M.tshift) * M.ta;
+  // Reverse sweep of a recurrence chunk by moments.  With z_k = z0 + k dz and
+  // t_k = t0 + k dt (k = 0..K-1 known constants), the adjoint sums need only
+  //   U_l = sum_k mb_k e_k k^l (l = 0..2) per Gaussian:
+  //     sum mb G z   = A (z0 U_0 + dz U_1)
+  //     sum mb G z^2 = A (z0^2 U_0 + 2 z0 dz U_1 + dz^2 U_2)
+  //   T_l = sum_k mb_k k^l for the polynomial (sum mb t^j by the binomial
+  //   expansion of (t0 + k dt)^j), or sum_k mb_k E_k k^l (l < 2) for the
+  //   exponential (sum mb E t = t0 T_0 + dt T_1),
+  // expanded once at the end of the chunk: a multiply-add per moment per bin
+  // instead of forming z and t powers per bin.
+  constexpr bool MOM = RECUR && GRAD;
+  constexpr int NT = (BKG == BKG_EXP) ? 2 : (S::NB > 0 ? S::NB : 1);
+  double U[G1][3], T[NT];
+  if constexpr (MOM) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) U[g][0] = U[g][1] = U[g][2] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) T[j] = 0.0;
+  }
   double Eb = 0.0;  // exponential background at the current bin (recurrence)
   if constexpr (RECUR && BKG == BKG_EXP) {
     const double a0 = fma(M.c[1], t0, M.c[0]);
@@ -117,7 +136,31 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
     flags |= dom ? ST_DOMAIN : 0;
     lk[k] = l;
     acc[0] = fma(w[k], l, acc[0]);
-    if constexpr (GRAD) {
+    if constexpr (MOM) {
+      // ---- reverse sweep, moment form (expanded after the loop) ----
+      const double mb = w[k] * ub;
+      const double kd = static_cast<double>(k), k2 = kd * kd;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const double u = mb * ek[g];
+        U[g][0] += u;
+        U[g][1] = fma(u, kd, U[g][1]);
+        U[g][2] = fma(u, k2, U[g][2]);
+      }
+      if constexpr (BKG == BKG_EXP) {
+        const double eb = mb * E;
+        T[0] += eb;
+        T[1] = fma(eb, kd, T[1]);
+      } else if constexpr (S::NB > 0) {
+        T[0] += mb;
+        double kp = kd;
+#pragma unroll
+        for (int j = 1; j < S::NB; ++j) {
+          T[j] = fma(mb, kp, T[j]);
+          kp *= kd;
+        }
+      }
+    } else if constexpr (GRAD) {
       // ---- reverse sweep: mu_bar = w ubar ----
       const double mb = w[k] * ub;
 #pragma unroll
@@ -151,6 +194,42 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
       for (int g = 0; g < NG; ++g) {
         e[g] *= r[g];
         r[g] *= M.D[g];
+      }
+    }
+  }
+  if constexpr (MOM) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const double dz = M.dz[g];
+      acc[1 + 3 * g] += U[g][0];
+      const double s1 = fma(dz, U[g][1], z0[g] * U[g][0]);  // sum mb e z
+      const double s2 = fma(z0[g], fma(2.0 * dz, U[g][1], z0[g] * U[g][0]), dz * dz * U[g][2]);
+      acc[2 + 3 * g] = fma(M.A[g], s1, acc[2 + 3 * g]);
+      acc[3 + 3 * g] = fma(M.A[g], s2, acc[3 + 3 * g]);
+    }
+    constexpr int k0 = 1 + 3 * NG;
+    if constexpr (BKG == BKG_EXP) {
+      acc[k0] += T[0];
+      acc[k0 + 1] += fma(M.dt, T[1], t0 * T[0]);
+    } else if constexpr (S::NB > 0) {
+      // sum_k mb (t0 + k dt)^j = sum_l C(j, l) t0^(j-l) dt^l T_l
+      constexpr double C[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+      double D[S::NB];
+      double dtp = 1.0;
+#pragma unroll
+      for (int l = 0; l < S::NB; ++l) {
+        D[l] = dtp * T[l];
+        dtp *= M.dt;
+      }
+#pragma unroll
+      for (int j = 0; j < S::NB; ++j) {
+        double sj = 0.0, t0p = 1.0;
+#pragma unroll
+        for (int l = j; l >= 0; --l) {
+          sj = fma(C[j][l] * t0p, D[l], sj);
+          t0p *= t0;
+        }
+        acc[k0 + j] += sj;
       }
     }
   }
