@@ -94,16 +94,21 @@ __device__ __forceinline__ void write_outputs(const NllArgs& a, const M& model, 
 // must leave room for (waves per SIMD).
 // Bins per thread per step (K) and waves per SIMD (W) the 1D kernel is built
 // for.  Every bin of a chunk is interleaved with the others, so registers
-// grow with K: 16-bin chunks need ~300 VGPRs and run one wave per SIMD.
-// Measured on the 1e7-bin two-Gaussian workload: 12-bin chunks at two waves
-// per SIMD (252 VGPRs) are 7% faster while the histogram stays in the
-// last-level cache, but 15% slower when every call reads it from HBM (51.8
-// vs 59.7 us); the HBM-resident case is the one the kernel is built for.
+// grow with K.  Measured with every call reading its 1e7 bins from HBM:
+//   two Gaussians + cubic, Poisson: 16 bins at two waves per SIMD (256
+//     VGPRs, a few spilled outside the chunk loop) 44.0 us, at one wave
+//     47.3 us; 12 bins at two waves 59.7 us (12-bin chunks win only while
+//     the histogram stays in the last-level cache);
+//   other Poisson models with up to two Gaussians: two waves 1-3% faster;
+//   two Gaussians + line, Neyman (no log, about half the work per bin):
+//     two waves 41.8 us, one wave 27.0 us.
+// So two waves for the Poisson objective with up to two Gaussians, one wave
+// otherwise (three or more Gaussians need well over 256 VGPRs at 16 bins).
 // K is a multiple of 4 (16-byte loads).
-template <int NG>
+template <int NG, int OBJ>
 struct Chunking {
   static constexpr int K = 16;
-  static constexpr int W = 1;
+  static constexpr int W = (NG <= 2 && OBJ == OBJ_POISSON) ? 2 : 1;
   static_assert(K % 4 == 0, "chunk must be a multiple of 4 bins");
 };
 constexpr int chunk_bins(int) { return 16; }
@@ -201,8 +206,8 @@ __device__ __forceinline__ void stream_chunks(const NllArgs& a, const Model1D<NG
 }
 
 template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN>
-__global__ __launch_bounds__(kBlock, Chunking<NG>::W) void k_nll_1d(NllArgs a) {
-  constexpr int K = Chunking<NG>::K;
+__global__ __launch_bounds__(kBlock, (Chunking<NG, OBJ>::W)) void k_nll_1d(NllArgs a) {
+  constexpr int K = Chunking<NG, OBJ>::K;
   using S = Shape1D<NG, BKG>;
   constexpr int NV = GRAD ? S::P + 1 : 1;
   const int64_t nb = a.nx;
