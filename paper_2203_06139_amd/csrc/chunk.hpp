@@ -23,9 +23,9 @@ namespace hf {
 
 // l(n, mu) and ubar = dl/dmu; returns true for a domain error.  Domain bins
 // are only flagged: the kernel then reports L = +inf and a NaN gradient, so
-// the common path carries no selects.  mu and n/mu are clamped to a tiny
-// positive value before the division and the log, which also makes the empty
-// bin (n = 0) come out exactly as l = mu, ubar = 1 (including mu = 0).
+// the common path carries no selects.  mu is clamped to a tiny positive
+// value before the division; the empty bin (n = 0) then comes out exactly as
+// l = mu, ubar = 1 (including mu = 0), the log of r = 0 being finite.
 template <int OBJ, bool F32BIN>
 __device__ __forceinline__ bool objective_t(double n, double mu, const double2* __restrict__ lut,
                                             double& l, double& ub) {
@@ -48,10 +48,13 @@ __device__ __forceinline__ bool objective_t(double n, double mu, const double2* 
   } else {
     // Poisson, saturated: l = mu - n + n ln(n/mu) (n > 0), l = mu (n = 0)
     const double r = div_fast<F32BIN>(n, fmax(mu, kTiny));
-    const double lg = log_lut<F32BIN>(fmax(r, kTiny), lut);
+    const double lg = log_lut<F32BIN>(r, lut);
     l = fma(n, lg, mu - n);
     ub = 1.0 - r;
-    return (mu < 0.0) || (mu == 0.0 && n > 0.0);
+    // domain: mu < 0, or mu = 0 with n > 0, i.e. mu below 0 (n = 0) or below
+    // the smallest positive double (n > 0) -- one min and one compare
+    constexpr double kDenormMin = 4.9406564584124654e-324;
+    return mu < fmin(n, kDenormMin);
   }
 }
 

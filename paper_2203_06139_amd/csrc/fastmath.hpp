@@ -15,9 +15,11 @@
 //   log_lut    x = 2^e m, m in [1,2); a 1024-entry LDS table of 1/c_j and
 //              ln c_j at the midpoints c_j of the top 10 mantissa bits gives
 //              f = m/c_j - 1 with |f| < 2^-11, and ln(1+f) is a degree-4
-//              polynomial (|f|^5/5 < 1e-17).  Table entries with c_j >= 1.5 store ln(c_j/2) and
-//              bump e, so arguments just below 1 do not cancel against ln 2.
-// Inputs must be finite; log_lut and div_fast need positive normal numbers.
+//              polynomial (|f|^5/5 < 1e-17).  Table entries with c_j >= 1.5
+//              store ln(c_j/2) and bump e, so arguments just below 1 do not
+//              cancel against ln 2.  log_lut(0) is finite (about -709): an
+//              empty bin's n ln(n/mu) term is 0 * finite = 0.
+// Inputs must be finite; div_fast needs a positive normal divisor.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,6 +30,7 @@ constexpr double kLog2e = 1.4426950408889634074;
 // ln 2 split so that k * kLn2Hi is exact for |k| < 2^11 (trailing zero bits).
 constexpr double kLn2Hi = 6.93147180369123816490e-01;
 constexpr double kLn2Lo = 1.90821492927058770002e-10;
+constexpr double kLn2 = 6.93147180559945309417e-01;
 
 constexpr int kLogLutBits = 10;
 constexpr int kLogLut = 1 << kLogLutBits;
@@ -113,8 +116,11 @@ __device__ __forceinline__ double log_lut(double x, const double2* __restrict__ 
     p = fma(p, f, -0.5);
     p = fma(p, f, 1.0);
   }
+  // e ln 2 in one rounding: e = 0 for arguments in [0.75, 1.5), where the
+  // objective cancels and needs the log to the last bit; elsewhere |ln x| >
+  // 0.28 and the term it enters is large, so ~1e-16 relative is ample.
   const double ed = static_cast<double>(e);
-  return fma(ed, kLn2Hi, t.y) + fma(ed, kLn2Lo, p * f);
+  return fma(p, f, fma(ed, kLn2, t.y));
 }
 
 }  // namespace hf
