@@ -92,7 +92,9 @@ __global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_2d(NllArgs a) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
-  const double seed = (a.grad_w_out && a.seed) ? a.seed[0] : 1.0;
+  const double gseed = a.seed ? a.seed[0] : 1.0;  // adjoint of L (seeds theta and w)
+  const double seed = a.grad_w_out ? gseed : 1.0;
+  const bool finite = all_finite(a.theta, a.P);
   const int64_t nx = a.nx;
   const int64_t cpr = (nx + K - 1) / K;  // chunks per row
   const int64_t nitems = cpr * a.ny;
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_2d(NllArgs a) {
   __shared__ double tot[NV];
   __shared__ int totf;
   if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
-    write_outputs<NV>(a, M, tot, totf);
+    write_outputs<NV>(a, M, tot, totf, finite, gseed);
 }
 
 template <int OBJ, bool GRAD, bool F32BIN>

@@ -70,11 +70,13 @@ __device__ __forceinline__ double load_count1(const NllArgs& a, int64_t i) {
 // A non-finite theta makes every output NaN (and sets ST_NONFINITE), whatever
 // the clamped per-bin arithmetic produced; a domain error makes L = +inf and
 // the gradient NaN (the objective is not differentiable there).
+// `finite` (theta all finite) and `seed` are read in the kernel's prologue,
+// with theta: after the grid reduction's acquire they would be dependent
+// memory round trips at the very end of the call.
 template <int NV, class M>
 __device__ __forceinline__ void write_outputs(const NllArgs& a, const M& model, const double* tot,
-                                              int totf) {
+                                              int totf, bool finite, double seed) {
   const int k = threadIdx.x;
-  const bool finite = all_finite(a.theta, a.P);
   const double nan = __builtin_nan("");
   const bool domain = (totf & ST_DOMAIN) != 0;
   if (k == 0) {
@@ -82,7 +84,6 @@ __device__ __forceinline__ void write_outputs(const NllArgs& a, const M& model, 
     if (a.status_out) a.status_out[0] = totf | (finite ? 0 : ST_NONFINITE);
   }
   if (NV > 1 && k >= 1 && k < NV) {
-    const double seed = a.seed ? a.seed[0] : 1.0;
     const bool free = (a.free_mask == 0u) || ((a.free_mask >> (k - 1)) & 1u);
     a.grad_out[k - 1] =
         (!finite || domain) ? nan : (free ? tot[k] * model.final_factor(k) * seed : 0.0);
@@ -234,7 +235,9 @@ __global__ __launch_bounds__(kBlock, (Chunking<NG, OBJ>::W)) void k_nll_1d(NllAr
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
-  const double seed = (a.grad_w_out && a.seed) ? a.seed[0] : 1.0;
+  const double gseed = a.seed ? a.seed[0] : 1.0;  // adjoint of L (seeds theta and w)
+  const double seed = a.grad_w_out ? gseed : 1.0;
+  const bool finite = all_finite(a.theta, a.P);
 
   if (spec) {
     stream_chunks<NG, BKG, OBJ, GRAD, F32BIN, true>(a, M, lut, nfull, tid, stride, seed, first, acc,
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(kBlock, (Chunking<NG, OBJ>::W)) void k_nll_1d(NllAr
   __shared__ double tot[NV];
   __shared__ int totf;
   if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
-    write_outputs<NV>(a, M, tot, totf);
+    write_outputs<NV>(a, M, tot, totf, finite, gseed);
 }
 
 template <class K>
