@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fastmath.hpp"
+
 namespace hf {
 
 enum : int { OBJ_NEYMAN = 0, OBJ_PEARSON = 1, OBJ_POISSON = 2 };
@@ -73,7 +75,7 @@ struct Model1D {
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
       dz[g] = h * is[g];
-      D[g] = exp(-dz[g] * dz[g]);
+      D[g] = exp_fast(-dz[g] * dz[g]);
       recur = recur && (K * fabs(dz[g]) <= 1.0);
     }
     dt = h * ta;
@@ -81,7 +83,7 @@ struct Model1D {
     if constexpr (BKG == BKG_EXP) {
       // E_{k+1} = E_k exp(b1 dt): exact ratio on the grid; K |b1 dt| <= 1
       // keeps q^K within [1/e, e], so the product loses no range
-      qE = exp(c[1] * dt);
+      qE = exp_fast(c[1] * dt);
       recur = recur && (K * fabs(c[1] * dt) <= 1.0);
     }
   }
