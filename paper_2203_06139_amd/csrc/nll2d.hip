@@ -29,18 +29,24 @@ __device__ __forceinline__ void chunk_2d(const Model2D& M, const double2* __rest
     r = F32BIN ? exp_hw32(a0) : exp_fast(a0);
     Dw = M.Dw;
   }
+  // Reverse sweep of a recurrence piece by moments: only u varies along the
+  // row (u_k = u0 + k du), and every adjoint term is mb e times a polynomial
+  // of degree <= 2 in u, so E_l = sum_k mb_k e_k k^l (l = 0..2) and
+  // sum_k mb_k suffice; they are expanded after the loop.
+  constexpr bool MOM = RECUR && GRAD;
+  double E0 = 0.0, E1 = 0.0, E2 = 0.0, Mb = 0.0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     // bins past len (short row tail, !RECUR only) are computed and masked
     const bool in = RECUR || k < len;
     // ---- forward sweep ----
-    const double u = fma(static_cast<double>(k), du, u0);
-    const double uv = u * v;
-    const double Q = (fma(u, u, v * v) - 2.0 * M.rho * uv) * M.invD;
-    double ek;
+    double ek, u = 0.0, uv = 0.0, Q = 0.0;
     if constexpr (RECUR) {
       ek = e;
     } else {
+      u = fma(static_cast<double>(k), du, u0);
+      uv = u * v;
+      Q = (fma(u, u, v * v) - 2.0 * M.rho * uv) * M.invD;
       ek = F32BIN ? exp_hw32(-0.5 * Q) : exp_fast(-0.5 * Q);
     }
     const double G = M.A * ek;
@@ -51,7 +57,15 @@ __device__ __forceinline__ void chunk_2d(const Model2D& M, const double2* __rest
     l = in ? l : 0.0;
     lk[k] = l;
     acc[0] = fma(w[k], l, acc[0]);
-    if constexpr (GRAD) {
+    if constexpr (MOM) {
+      const double mb = w[k] * ub;
+      const double kd = static_cast<double>(k);
+      const double t = mb * ek;
+      E0 += t;
+      E1 = fma(t, kd, E1);
+      E2 = fma(t, kd * kd, E2);
+      Mb += mb;
+    } else if constexpr (GRAD) {
       // ---- reverse sweep: mu_bar = w ubar ----
       const double mb = in ? w[k] * ub : 0.0;
       acc[1] = fma(mb, ek, acc[1]);  // A
@@ -72,6 +86,21 @@ __device__ __forceinline__ void chunk_2d(const Model2D& M, const double2* __rest
       e *= r;
       r *= Dw;
     }
+  }
+  if constexpr (MOM) {
+    // with g = mb G = A mb e: S0 = sum g, Su = sum g u, Su2 = sum g u^2
+    const double su = fma(du, E1, u0 * E0);
+    const double su2 = fma(u0, fma(2.0 * du, E1, u0 * E0), du * du * E2);
+    const double S0 = M.A * E0, Su = M.A * su, Su2 = M.A * su2;
+    const double rho = M.rho;
+    acc[1] += E0;                                              // A
+    acc[2] += fma(-rho * v, S0, Su);                           // sum g (u - rho v)
+    acc[3] += fma(v, S0, -rho * Su);                           // sum g (v - rho u)
+    acc[4] += fma(-rho * v, Su, Su2);                          // sum g (u - rho v) u
+    acc[5] += v * fma(v, S0, -rho * Su);                       // sum g (v - rho u) v
+    const double sq = fma(v * v, S0, fma(-2.0 * rho * v, Su, Su2));  // sum g (u^2 - 2 rho u v + v^2)
+    acc[6] += fma(v, Su, -rho * M.invD * sq);                  // sum g (u v - rho Q)
+    acc[7] += Mb;                                              // c
   }
 }
 
