@@ -165,13 +165,15 @@ def main():
     ap.add_argument("--train-fits", type=int, default=1_000_000,
                     help="learned workload: plain fits the initialiser is trained on")
     ap.add_argument("--epochs", type=int, default=8, help="learned workload: training epochs")
-    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned", "gradient"],
+    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned", "gradient",
+                                           "fisher"],
                     default="large1d",
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
                          "fit_batch; learned: plain vs learned-initialiser fits of that batch; "
                          "gradient: fits with the reverse-mode gradient vs central differences "
-                         "for 1..4 Gaussians")
+                         "for 1..4 Gaussians; fisher: the expected Hessian of the 1e7-bin "
+                         "workload (and of the 2048^2 one)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc counter CSVs of a "
                          "run with --copy-calibration (no GPU work)")
@@ -209,6 +211,8 @@ def main():
         return bench_learned(args, hf, datagen, np, torch, dev)
     if args.workload == "gradient":
         return bench_gradient(args, hf, datagen, np, torch, dev)
+    if args.workload == "fisher":
+        return bench_fisher(args, hf, datagen, np, torch, dev)
     obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
 
@@ -391,6 +395,49 @@ def bench_hist2d(args, hf, datagen, np, torch, dev):
                                                "Poisson NLL + gradient + weight gradient",
                                       nbins=nb, precision=args.precision),
                           hbm_gbs=12 * nb / (ms * 1e-3) / 1e9)), flush=True)
+
+
+def bench_fisher(args, hf, datagen, np, torch, dev):
+    """Expected Hessian F = J^T diag(w c) J of the 1e7-bin two-Gaussian +
+    cubic workload (P = 10: 55 upper-triangle FMAs per bin), then of the
+    2048^2 2D workload (P = 7: 28 per bin).  The Poisson F does not read the
+    counts (c = 1/mu), so these kernels are bound by the FP64 vector units;
+    the figure reported is the contraction's algorithmic FP64 rate,
+    2 P(P+1)/2 flops per bin, against the 78.6 TFLOP/s FP64 vector peak."""
+    obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
+    c1 = datagen.large_fit_case()
+    c2 = datagen.hist2d_case()
+    work = [
+        ("1D histogram, 1e7 bins on [0,100], two Gaussians + cubic (10 parameters)",
+         hf.make_hist(c1["counts"], c1["range"], device=dev), hf.Model.from_spec(c1["spec"]),
+         c1["theta_eval"], c1["counts"].size),
+        ("2D histogram 2048x2048, correlated Gaussian + constant (7 parameters), f32 weights",
+         hf.make_hist(c2["counts"], (0.0, 1.0), (0.0, 1.0), weights=c2["weights"], device=dev),
+         hf.Model(hf.GAUSS2D), c2["theta_eval"], c2["counts"].size),
+    ]
+    for name, h, m, th, nb in work:
+        P = m.nparams
+        tht = torch.as_tensor(th, dtype=torch.float64, device=dev)
+        out = torch.empty((P, P), dtype=torch.float64, device=dev)
+
+        def step(k):
+            hf.nll_fisher(h, m, tht, objective=obj, out=out)
+
+        for k in range(args.warmup):
+            step(k)
+        ms = time_graph(torch, step, args.steps)
+        flops = 2.0 * (P * (P + 1) // 2) * nb
+        achieved = flops / (ms * 1e-3) / 1e12
+        print(json.dumps(dict(
+            metric="bins*Fisher/s", value=nb / (ms * 1e-3), unit="bins/s", n_gpus=1,
+            steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
+            scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+            config=dict(workload=name + ", expected Hessian, " + args.objective, nbins=nb,
+                        nparams=P),
+            roofline=dict(bound="alu", achieved=achieved, peak=78.6, unit="TFLOP/s",
+                          frac=achieved / 78.6, traffic=None,
+                          note="contraction flops only (2 per upper-triangle entry per bin)"))),
+              flush=True)
 
 
 def fits_cpu_baseline(c, theta0, np, seconds=10.0):

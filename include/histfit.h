@@ -159,6 +159,39 @@ int nll_grad(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t ob
              double* grad_out, float* grad_w_out, uint32_t free_mask, int32_t* status_out,
              hf_stream_t stream);
 
+/* Expected Hessian (Fisher information) of the objective at theta: the
+ * second-derivative matrix that the paper (sec. 4) leaves to numerical
+ * differentiation, in the Gauss-Newton form that parameter errors use,
+ *   F_jk = sum_i w_i c_i (dmu_i/dtheta_j)(dmu_i/dtheta_k),
+ *   c_i = 1/mu_i (Poisson), 2/mu_i (Pearson), 2/n_i (Neyman, n_i > 0);
+ * bins whose c_i is not finite and positive are skipped.  Only the Neyman
+ * objective reads the counts.  FP64 throughout.
+ *   theta      device f64[P].
+ *   fisher_out device f64[P*P], row-major, OVERWRITTEN (symmetric); all NaN
+ *              when theta is not finite.
+ *   status_out device i32[1] or NULL: HF_ST_NONFINITE when theta is not
+ *              finite, else 0.
+ * Uses the context's reduction scratch, like nll_grad: calls on one context
+ * must not overlap in time.                                               */
+int hf_nll_fisher(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t objective,
+                  const double* theta, double* fisher_out, int32_t* status_out,
+                  hf_stream_t stream);
+
+/* Parameter covariance from B Fisher matrices (hf_nll_fisher's layout):
+ * for the free parameters (free_mask bit set; 0 = all),
+ *   cov = 2 UP F^-1,  UP = 1/2 (Poisson NLL, which has no factor 2) or 1
+ *   (chi-square): the inverse curvature at the level where the objective
+ *   rises by UP, so sqrt(cov_kk) is the usual one-sigma error;
+ * rows and columns of fixed parameters are 0.  The inverse is taken by
+ * Cholesky of F scaled to unit diagonal; a pivot not above 1e-12 (or a
+ * non-positive diagonal entry) makes the free entries NaN and status 1.
+ *   fisher     device f64[B][P][P];  cov_out device f64[B][P][P];
+ *   status_out device i32[B] or NULL (0 ok, 1 not positive definite).
+ *   P          1..16.                                                      */
+int hf_fisher_covariance(hf_ctx* ctx, int32_t B, int32_t P, int32_t objective,
+                         const double* fisher, uint32_t free_mask, double* cov_out,
+                         int32_t* status_out, hf_stream_t stream);
+
 /* Options of the fitter: BFGS on the inverse Hessian in scaled coordinates,
  * backtracking Armijo line search (c1 = 1e-4, step halved up to ls_max
  * times), stop when EDM = g^T H g / 2 < max(edm_tol, 4 eps |L|).  The

@@ -143,6 +143,28 @@ def fisher(model: Model, objective: int, counts, theta, range4, weights=None):
     return F.reshape(P, P)
 
 
+def covariance(F, objective: int, free_mask: int = 0):
+    """Parameter covariance from an expected Hessian: cov = 2 UP inv(F) over
+    the free parameters (bit k of free_mask set, or all when 0), zero rows and
+    columns for fixed ones.  UP is the rise of the objective that defines one
+    standard error: 1/2 for the Poisson NLL (written without the factor 2),
+    1 for a chi-square.  Returns (cov, ok); ok is False (cov NaN in the free
+    block) when the free block is not positive definite."""
+    F = np.asarray(F, dtype=np.float64)
+    P = F.shape[0]
+    free = [k for k in range(P) if free_mask == 0 or (free_mask >> k) & 1]
+    cov = np.zeros((P, P))
+    Ff = F[np.ix_(free, free)]
+    scale = 1.0 if objective == 2 else 2.0
+    try:
+        np.linalg.cholesky(Ff)
+        ok = bool(np.all(np.diag(Ff) > 0))
+    except np.linalg.LinAlgError:
+        ok = False
+    cov[np.ix_(free, free)] = scale * np.linalg.inv(Ff) if ok else np.nan
+    return cov, ok
+
+
 def model_eval(model: Model, theta, shape, range4):
     """mu at every bin centre; shape = (nx,) or (ny, nx)."""
     nx = shape[-1]

@@ -129,7 +129,10 @@ def load():
     L.hf_fit_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]
     L.hf_fit_max_cache_bins.argtypes = [vp, ctypes.POINTER(HfModel), i32, i32]
-    for fn in (L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
+    L.hf_nll_fisher.argtypes = [vp, ctypes.POINTER(HfHist), ctypes.POINTER(HfModel), i32, vp, vp,
+                                vp, vp]
+    L.hf_fisher_covariance.argtypes = [vp, i32, i32, i32, vp, ctypes.c_uint32, vp, vp, vp]
+    for fn in (L.hf_nll_fisher, L.hf_fisher_covariance, L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
                L.hf_target_to_theta, L.hf_mlp_forward, L.hf_mlp_train_step, L.hf_fit_set_tuning,
                L.hf_fit_get_tuning, L.hf_fit_max_cache_bins):
         fn.restype = ctypes.c_int
@@ -306,6 +309,51 @@ def nll_grad(hist: Hist, model: Model, theta, objective=POISSON, precision=FP64,
                          _ptr(grad_w_out), free_mask, _ptr(status), _stream(dev))
     _check(rc, ctx)
     return nll_out, grad_out, grad_w_out
+
+
+def nll_fisher(hist: Hist, model: Model, theta, objective=POISSON, out=None, status=None):
+    """Expected Hessian F = sum_i w_i c_i (dmu_i/dtheta)(dmu_i/dtheta)^T at
+    theta as a device f64[P, P] tensor (c_i = 1/mu Poisson, 2/mu Pearson,
+    2/n Neyman)."""
+    import torch
+    dev = hist.counts.device
+    ctx = context(dev.index)
+    th = _dev_tensor(theta, torch.float64, dev, "theta")
+    _check_theta(th, model)
+    _check_hist_sizes(hist)
+    P = th.numel()
+    if out is None:
+        out = torch.empty((P, P), dtype=torch.float64, device=dev)
+    elif out.numel() != P * P or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous f64 tensor of P*P values")
+    rc = load().hf_nll_fisher(ctx, ctypes.byref(hist.c()), ctypes.byref(model.c()), objective,
+                              _ptr(th), _ptr(out), _ptr(status), _stream(dev))
+    _check(rc, ctx)
+    return out
+
+
+def fisher_covariance(fisher, objective=POISSON, free_mask=0, out=None, status=None):
+    """Covariance 2 UP F^-1 over the free parameters of each [P, P] Fisher
+    matrix in `fisher` ([P, P] or [B, P, P], device f64); UP = 1/2 for the
+    Poisson NLL, 1 for the chi-squares.  Returns (cov, status) with status
+    1 where the free block is not positive definite (cov NaN there)."""
+    import torch
+    F = fisher
+    if F.dtype != torch.float64 or F.dim() not in (2, 3) or F.shape[-1] != F.shape[-2]:
+        raise ValueError("fisher must be f64 [P, P] or [B, P, P]")
+    F = F.contiguous()
+    dev = F.device
+    ctx = context(dev.index)
+    P = F.shape[-1]
+    B = 1 if F.dim() == 2 else F.shape[0]
+    out = torch.empty_like(F) if out is None else out
+    if out.shape != F.shape or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous f64 tensor shaped like fisher")
+    status = torch.empty(B, dtype=torch.int32, device=dev) if status is None else status
+    rc = load().hf_fisher_covariance(ctx, B, P, objective, _ptr(F), free_mask, _ptr(out),
+                                     _ptr(status), _stream(dev))
+    _check(rc, ctx)
+    return out, status
 
 
 @dataclass

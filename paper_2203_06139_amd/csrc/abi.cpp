@@ -12,6 +12,7 @@
 #include <string>
 
 #include "../../include/histfit.h"
+#include "fisher_kernels.hpp"
 #include "fit_kernels.hpp"
 #include "mlp.hpp"
 #include "nll_kernels.hpp"
@@ -29,8 +30,10 @@ static_assert(HF_MLP_IN == hf::kMlpIn && HF_MLP_HIDDEN == hf::kMlpHidden && HF_M
 
 namespace {
 
-// Largest reduction width: P + 1 with P <= 16.
-constexpr int kMaxNV = 17;
+// Largest reduction width: P + 1 with P <= 16 for the objective, 64
+// upper-triangle entries per pass for the Fisher matrix.
+constexpr int kMaxNV = 64;
+static_assert(hf::kFisherQ <= kMaxNV, "partials scratch");
 // Upper bound on the objective kernels' grid; the partial-sum scratch is
 // sized for it once, at context creation, so no call allocates afterwards.
 constexpr int kMaxGrid = 8192;
@@ -42,6 +45,7 @@ struct hf_ctx {
   int num_cu = 0;
   int blocks_per_cu = 0;  // 0: as many as the kernel's occupancy allows
   std::map<hf::LaunchFn, int> occupancy;
+  std::map<hf::FisherFn, int> fisher_occupancy;
   std::string err;
   double* part = nullptr;
   int32_t* part_flags = nullptr;
@@ -322,6 +326,99 @@ HF_EXPORT int nll_grad(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t o
                        hf_stream_t stream) {
   return run_objective(c, h, m, obj, prec, theta, seed, nll_out, grad_out, grad_w_out, free_mask,
                        status_out, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+HF_EXPORT int hf_nll_fisher(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj,
+                            const double* theta, double* fisher_out, int32_t* status_out,
+                            hf_stream_t stream_) {
+  if (!c) return HF_EINVAL;
+  int rc = check_model(c, m);
+  if (rc) return rc;
+  const bool two_d = m->kind == HF_GAUSS2D;
+  rc = check_hist(c, h, two_d);
+  if (rc) return rc;
+  if (obj < HF_NEYMAN || obj > HF_POISSON) return fail(c, HF_EINVAL, "objective %d unknown", obj);
+  if (!theta) return fail(c, HF_EINVAL, "theta is NULL");
+  if (!fisher_out) return fail(c, HF_EINVAL, "fisher_out is NULL");
+  rc = use_device(c);
+  if (rc) return rc;
+  const bool ney = obj == HF_NEYMAN;
+  hf::FisherFn fn = nullptr;
+  if (two_d) {
+    fn = hf::pick_fisher_2d(ney);
+  } else {
+    switch (m->n_gauss) {
+      case 0: fn = hf::pick_fisher_ng0(bkg_code(m), ney); break;
+      case 1: fn = hf::pick_fisher_ng1(bkg_code(m), ney); break;
+      case 2: fn = hf::pick_fisher_ng2(bkg_code(m), ney); break;
+      case 3: fn = hf::pick_fisher_ng3(bkg_code(m), ney); break;
+      case 4: fn = hf::pick_fisher_ng4(bkg_code(m), ney); break;
+      default: break;
+    }
+  }
+  if (!fn) return fail(c, HF_EUNSUPPORTED, "no Fisher kernel for this model");
+  const hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  hf::FisherArgs a{};
+  a.counts = h->counts;
+  a.weights = h->weights;
+  a.nx = h->nx;
+  a.ny = two_d ? h->ny : 1;
+  a.dtype = h->counts_dtype;
+  a.P = nparams(m);
+  a.hx = (h->xhi - h->xlo) / static_cast<double>(h->nx);
+  a.x0 = h->xlo + 0.5 * a.hx;
+  if (two_d) {
+    a.hy = (h->yhi - h->ylo) / static_cast<double>(h->ny);
+    a.y0 = h->ylo + 0.5 * a.hy;
+  }
+  a.cfac = obj == HF_POISSON ? 1.0 : 2.0;
+  a.theta = theta;
+  a.fisher_out = fisher_out;
+  a.status_out = status_out;
+  a.t_shift = m->t_shift;
+  a.t_scale = m->t_scale;
+  a.part = c->part;
+  a.part_flags = c->part_flags;
+  a.ticket = c->ticket;
+  auto it = c->fisher_occupancy.find(fn);
+  if (it == c->fisher_occupancy.end()) {
+    int occ = 0;
+    hipError_t e = fn(a, 0, 0, stream, &occ);
+    if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
+    it = c->fisher_occupancy.emplace(fn, occ < 1 ? 1 : occ).first;
+  }
+  const int per_cu = c->blocks_per_cu > 0 ? c->blocks_per_cu : it->second;
+  const int64_t items_bins =
+      two_d ? ((a.nx + hf::kFisherChunk - 1) / hf::kFisherChunk) * hf::kFisherChunk * a.ny : a.nx;
+  const int grid = objective_grid(c, items_bins, hf::kFisherChunk, per_cu);
+  const int passes = hf::fisher_passes(a.P);
+  for (int p = 0; p < passes; ++p) {
+    hipError_t e = fn(a, p, grid, stream, nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  }
+  return HF_OK;
+}
+
+HF_EXPORT int hf_fisher_covariance(hf_ctx* c, int32_t B, int32_t P, int32_t obj,
+                                   const double* fisher, uint32_t free_mask, double* cov_out,
+                                   int32_t* status_out, hf_stream_t stream) {
+  if (!c) return HF_EINVAL;
+  if (B < 0) return fail(c, HF_EINVAL, "B must be >= 0");
+  if (P < 1 || P > 16) return fail(c, HF_EINVAL, "P %d outside 1..16", P);
+  if (obj < HF_NEYMAN || obj > HF_POISSON) return fail(c, HF_EINVAL, "objective %d unknown", obj);
+  if (B > 0 && (!fisher || !cov_out)) return fail(c, HF_EINVAL, "fisher and cov_out must be non-NULL");
+  if (P < 32 && (free_mask >> P) != 0u)
+    return fail(c, HF_EINVAL, "free_mask has bits at or above P");
+  int rc = use_device(c);
+  if (rc) return rc;
+  // F is the objective's expected curvature; one standard error is where the
+  // objective rises by UP = 1/2 (Poisson NLL without the factor 2) or 1
+  // (chi-square), so cov = 2 UP F^-1
+  const double scale = obj == HF_POISSON ? 1.0 : 2.0;
+  hipError_t e = hf::fisher_covariance(B, P, fisher, free_mask, scale, cov_out, status_out,
+                                       reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return HF_OK;
 }
 
 HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,

@@ -137,6 +137,22 @@ struct Model2D {
   }
 };
 
+// Row and column of entry e of the upper triangle of a P x P matrix,
+// row-major (a <= b).
+template <int P>
+struct TriIndex {
+  static constexpr int N = P * (P + 1) / 2;
+  int a[N], b[N];
+  constexpr TriIndex() : a(), b() {
+    int e = 0;
+    for (int r = 0; r < P; ++r)
+      for (int c = r; c < P; ++c, ++e) {
+        a[e] = r;
+        b[e] = c;
+      }
+  }
+};
+
 // --------------------------------------------------------------------------
 // Deterministic reductions.
 // --------------------------------------------------------------------------

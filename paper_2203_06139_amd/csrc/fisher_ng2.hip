@@ -1,0 +1,8 @@
+// fisher_ng2.hip -- Fisher-information kernels of the 1D models with 2
+// Gaussian(s); one translation unit per Gaussian count so the instantiations
+// compile in parallel.
+#include "fisher_kernels.hpp"
+
+namespace hf {
+FisherFn pick_fisher_ng2(int bkg, bool ney) { return pick_fisher_ng<2>(bkg, ney); }
+}  // namespace hf

@@ -68,22 +68,6 @@ struct FitShared {
   int h;
 };
 
-// Row and column of entry e of the upper triangle of a P x P matrix,
-// row-major (a <= b).
-template <int P>
-struct TriIndex {
-  static constexpr int N = P * (P + 1) / 2;
-  int a[N], b[N];
-  constexpr TriIndex() : a(), b() {
-    int e = 0;
-    for (int r = 0; r < P; ++r)
-      for (int c = r; c < P; ++c, ++e) {
-        a[e] = r;
-        b[e] = c;
-      }
-  }
-};
-
 // Bins per thread per step of the fit's objective sweep.
 constexpr int kFitChunk = 4;
 

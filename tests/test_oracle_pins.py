@@ -497,3 +497,76 @@ def test_fisher_start_cuts_iterations_on_batch(orc):
     assert both.mean() > 0.9
     assert np.median(np.abs(r1[1] - r0[1])[both]) < 1e-6
     assert r1[3].mean() < 0.5 * r0[3].mean(), (r1[3].mean(), r0[3].mean())
+
+
+# ---------------------------------------------------------------------------
+# Parameter covariance from the expected Hessian
+# ---------------------------------------------------------------------------
+def test_covariance_constant_model_textbook_variances(orc):
+    """Poisson counts: the MLE of a constant is the mean, whose variance is
+    c/N.  Neyman: the fit is the weighted mean with sigma_i^2 = n_i, whose
+    variance is 1/sum(1/n_i).  Pearson: sigma_i^2 = mu, variance c/N."""
+    rng = np.random.default_rng(31)
+    n = rng.poisson(25.0, 300).astype(np.float64)
+    M = _const_model(orc)
+    N = n.size
+    chat = n.mean()
+    cov, ok = orc.covariance(orc.fisher(M, 2, n, [chat], (0, 1)), 2)
+    assert ok and cov[0, 0] == pytest.approx(chat / N, rel=1e-12)
+    cov, ok = orc.covariance(orc.fisher(M, 1, n, [chat], (0, 1)), 1)
+    assert ok and cov[0, 0] == pytest.approx(chat / N, rel=1e-12)
+    cov, ok = orc.covariance(orc.fisher(M, 0, n, [chat], (0, 1)), 0)
+    assert ok and cov[0, 0] == pytest.approx(1.0 / np.sum(1.0 / n), rel=1e-12)
+
+
+def test_covariance_neyman_line_is_the_least_squares_covariance(orc):
+    """A straight line fitted by Neyman's chi-square is weighted least squares
+    with sigma_i^2 = n_i; its covariance is inv(Phi^T W Phi), W = diag(1/n)."""
+    rng = np.random.default_rng(32)
+    nb = 80
+    n = rng.poisson(60.0, nb).astype(np.float64) + 1.0
+    r = (0.0, 4.0)
+    M = orc.Model(1, 0, 1)
+    x = r[0] + (np.arange(nb) + 0.5) * (r[1] - r[0]) / nb
+    Phi = np.stack([np.ones(nb), x], axis=1)
+    expect = np.linalg.inv(Phi.T @ (Phi / n[:, None]))
+    cov, ok = orc.covariance(orc.fisher(M, 0, n, [60.0, 1.0], r), 0)
+    assert ok
+    np.testing.assert_allclose(cov, expect, rtol=1e-11)
+
+
+def test_covariance_free_mask_and_singular(orc):
+    F = np.array([[4.0, 1.0, 0.5], [1.0, 3.0, 0.2], [0.5, 0.2, 2.0]])
+    cov, ok = orc.covariance(F, 2, free_mask=0b101)
+    assert ok
+    sub = np.linalg.inv(F[np.ix_([0, 2], [0, 2])])
+    assert cov[1, :].tolist() == [0, 0, 0] and cov[:, 1].tolist() == [0, 0, 0]
+    np.testing.assert_allclose(cov[np.ix_([0, 2], [0, 2])], sub, rtol=1e-14)
+    cov, ok = orc.covariance(np.array([[1.0, 1.0], [1.0, 1.0 - 1e-300]]) - np.eye(2) * 1e-3, 0)
+    assert not ok and np.all(np.isnan(cov))
+
+
+@pytest.mark.parametrize("obj", [0, 2])
+def test_covariance_matches_the_spread_of_refits(orc, obj):
+    """Monte Carlo: refit many Poisson replicas of one Gaussian on a flat
+    background; the sample covariance of the fitted parameters must match
+    2 UP inv(F) at the truth (a factor-2 mistake in UP would be off by 100%).
+    With 600 replicas a variance is known to sqrt(2/599) = 6%."""
+    R, nb = 600, 60
+    r = (0.0, 6.0)
+    th = np.array([400.0, 3.0, 0.5, 80.0])
+    M = orc.Model(1, 1, 0)
+    mu = orc.model_eval(M, th, (nb,), r)
+    rng = np.random.default_rng(33)
+    counts = rng.poisson(np.tile(mu, (R, 1))).astype(np.float64)
+    off = np.arange(R + 1, dtype=np.int64) * nb
+    ranges = np.tile(np.array(r), (R, 1))
+    fits, _, st, _, _ = orc.fit_many(M, obj, counts.reshape(-1), off, ranges, np.tile(th, (R, 1)),
+                                     nthreads=8, hessian_init=1)
+    assert np.all(st == orc.FIT_CONVERGED)
+    emp = np.cov(fits.T)
+    cov, ok = orc.covariance(orc.fisher(M, obj, mu, th, r), obj)
+    assert ok
+    np.testing.assert_allclose(np.diag(emp), np.diag(cov), rtol=0.25)
+    corr = lambda C: C[0, 2] / math.sqrt(C[0, 0] * C[2, 2])  # amplitude-width correlation
+    assert abs(corr(emp) - corr(cov)) < 0.12
