@@ -166,14 +166,15 @@ def main():
                     help="learned workload: plain fits the initialiser is trained on")
     ap.add_argument("--epochs", type=int, default=8, help="learned workload: training epochs")
     ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned", "gradient",
-                                           "fisher"],
+                                           "fisher", "gradmap"],
                     default="large1d",
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
                          "fit_batch; learned: plain vs learned-initialiser fits of that batch; "
                          "gradient: fits with the reverse-mode gradient vs central differences "
                          "for 1..4 Gaussians; fisher: the expected Hessian of the 1e7-bin "
-                         "workload (and of the 2048^2 one)")
+                         "workload (and of the 2048^2 one); gradmap: the elementwise Gaussian "
+                         "gradient of 2^27 parameter sets")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc counter CSVs of a "
                          "run with --copy-calibration (no GPU work)")
@@ -213,6 +214,8 @@ def main():
         return bench_gradient(args, hf, datagen, np, torch, dev)
     if args.workload == "fisher":
         return bench_fisher(args, hf, datagen, np, torch, dev)
+    if args.workload == "gradmap":
+        return bench_gradmap(args, hf, np, torch, dev)
     obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
 
@@ -438,6 +441,49 @@ def bench_fisher(args, hf, datagen, np, torch, dev):
                           frac=achieved / 78.6, traffic=None,
                           note="contraction flops only (2 per upper-triangle entry per bin)"))),
               flush=True)
+
+
+def bench_gradmap(args, hf, np, torch, dev):
+    """Elementwise Gaussian and its gradient over 2^27 independent parameter
+    sets.  First the listing's configuration (per-element x and p, one shared
+    sigma, outputs dx and dp: 32 bytes per element), then every input per
+    element with every output (x, p, sigma and a seed in; g, dx, dp, dsigma
+    out: 64 bytes).
+    Both stream HBM: the roofline is the 8 TB/s peak."""
+    n = 1 << 27
+    gen = torch.Generator(device=dev).manual_seed(12)
+    p = torch.rand(n, dtype=torch.float64, device=dev, generator=gen) * 6 - 3
+    x = p + torch.randn(n, dtype=torch.float64, device=dev, generator=gen) * 2
+    s1 = torch.tensor([1.25], dtype=torch.float64, device=dev)
+    sn = torch.rand(n, dtype=torch.float64, device=dev, generator=gen) + 0.5
+    w = torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+    runs = [
+        ("listing: x, p per element, sigma shared; outputs dx, dp", 32,
+         lambda k: hf.gauss_grad_map(x, p, s1, want_g=False)),
+        ("all per element with a seed; outputs g, dx, dp, dsigma", 64,
+         lambda k: hf.gauss_grad_map(x, p, sn, seed=w, want_dsigma=True)),
+    ]
+    for name, bpe, step in runs:
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        # eager launches: the outputs are allocated per call by the binding
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for k in range(args.steps):
+            step(k)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        gbs = bpe * n / (ms * 1e-3) / 1e9
+        print(json.dumps(dict(
+            metric="elements*(g,grad)/s", value=n / (ms * 1e-3), unit="elements/s", n_gpus=1,
+            steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
+            scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+            config=dict(workload="elementwise Gaussian gradient, 2^27 parameter sets, " + name,
+                        n=n, bytes_per_element=bpe),
+            roofline=dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=gbs / HBM_PEAK_GBS, traffic=None))), flush=True)
 
 
 def fits_cpu_baseline(c, theta0, np, seconds=10.0):

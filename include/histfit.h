@@ -192,6 +192,35 @@ int hf_fisher_covariance(hf_ctx* ctx, int32_t B, int32_t P, int32_t objective,
                          const double* fisher, uint32_t free_mask, double* cov_out,
                          int32_t* status_out, hf_stream_t stream);
 
+/* Elementwise Gaussian and its reverse-mode gradient over n independent
+ * parameter sets: the device-function example of paper sec. 3 (Listing 1),
+ * one element per thread, generalised to shared parameters.  Per element,
+ * with d = x_i - p_i and s = sigma_i,
+ *   g_i = (2 pi)^(-1/2) s^(-a) exp(-d^2 / (2 s^2)),
+ *   a = 1/2 (HF_NORM_LISTING: the normalisation as the listing prints it)
+ *       or 1 (HF_NORM_PDF: the normal probability density);
+ * with upstream adjoint w_i (seed_i, or 1 when seed is NULL):
+ *   dx_i = w_i dg_i/dx_i = -w_i g_i d / s^2,  dp_i = -dx_i,
+ *   dsigma_i = w_i g_i (d^2 / s^3 - a / s).
+ * p (resp. sigma) is either per element (p_shared = 0: p is f64[n]) or one
+ * value for all elements (p_shared = 1: p is f64[1]).  A shared input's
+ * adjoint is the sum over the elements, dp_out[0] = sum_i dp_i, taken in a
+ * fixed order (deterministic); a per-element input's adjoint is per element.
+ *   x          device f64[n];  seed device f64[n] or NULL.
+ *   g_out, dx_out              device f64[n] or NULL (not computed).
+ *   dp_out, dsigma_out         device f64[n] (per element), f64[1] (shared),
+ *                              or NULL.  All outputs are OVERWRITTEN.
+ *   sigma must be positive for HF_NORM_LISTING (s^(-1/2)) and nonzero for
+ *   HF_NORM_PDF; other values follow IEEE arithmetic (NaN or inf).
+ * n may be 0 (shared adjoints are then 0).  Arrays that are all 16-byte
+ * aligned move as 16-byte vectors.  A call with a shared input uses the
+ * context's reduction scratch: calls on one context must not overlap.     */
+typedef enum { HF_NORM_LISTING = 0, HF_NORM_PDF = 1 } hf_gauss_norm;
+int hf_gauss_grad_map(hf_ctx* ctx, int64_t n, const double* x, const double* p, int32_t p_shared,
+                      const double* sigma, int32_t sigma_shared, int32_t norm, const double* seed,
+                      double* g_out, double* dx_out, double* dp_out, double* dsigma_out,
+                      hf_stream_t stream);
+
 /* Options of the fitter: BFGS on the inverse Hessian in scaled coordinates,
  * backtracking Armijo line search (c1 = 1e-4, step halved up to ls_max
  * times), stop when EDM = g^T H g / 2 < max(edm_tol, 4 eps |L|).  The

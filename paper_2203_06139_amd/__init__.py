@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhistfit.so")
 
 NEYMAN, PEARSON, POISSON = 0, 1, 2
+NORM_LISTING, NORM_PDF = 0, 1
 GAUSS_POLY, GAUSS_EXP, GAUSS2D = 1, 2, 3
 FP64, FP32_BIN = 0, 1
 U32, F32, F64 = 0, 1, 2
@@ -132,7 +133,8 @@ def load():
     L.hf_nll_fisher.argtypes = [vp, ctypes.POINTER(HfHist), ctypes.POINTER(HfModel), i32, vp, vp,
                                 vp, vp]
     L.hf_fisher_covariance.argtypes = [vp, i32, i32, i32, vp, ctypes.c_uint32, vp, vp, vp]
-    for fn in (L.hf_nll_fisher, L.hf_fisher_covariance, L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
+    L.hf_gauss_grad_map.argtypes = [vp, i64, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    for fn in (L.hf_gauss_grad_map, L.hf_nll_fisher, L.hf_fisher_covariance, L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
                L.hf_target_to_theta, L.hf_mlp_forward, L.hf_mlp_train_step, L.hf_fit_set_tuning,
                L.hf_fit_get_tuning, L.hf_fit_max_cache_bins):
         fn.restype = ctypes.c_int
@@ -354,6 +356,42 @@ def fisher_covariance(fisher, objective=POISSON, free_mask=0, out=None, status=N
                                      _ptr(status), _stream(dev))
     _check(rc, ctx)
     return out, status
+
+
+def gauss_grad_map(x, p, sigma, norm=NORM_LISTING, seed=None, want_g=True, want_dx=True,
+                   want_dp=True, want_dsigma=False):
+    """Elementwise g_i = (2 pi)^(-1/2) s^(-a) exp(-(x_i - p_i)^2 / (2 s^2)) and
+    its reverse-mode gradient with upstream adjoints `seed` (device f64[n] or
+    None for 1).  x is a device f64[n]; p and sigma are device f64[n] or a
+    single value (shared by every element, whose adjoint is then the sum over
+    the elements).  Returns (g, dx, dp, dsigma), None for the ones not asked
+    for."""
+    import torch
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or x.dim() != 1:
+        raise ValueError("x must be a 1-D f64 tensor")
+    dev = x.device
+    ctx = context(dev.index)
+    n = x.numel()
+    x = x.contiguous()
+    p = _dev_tensor(p, torch.float64, dev, "p").reshape(-1).contiguous()
+    s = _dev_tensor(sigma, torch.float64, dev, "sigma").reshape(-1).contiguous()
+    psh, ssh = int(p.numel() == 1), int(s.numel() == 1)
+    for name, t in (("p", p), ("sigma", s)):
+        if t.numel() not in (1, n):
+            raise ValueError("%s must have 1 or n values" % name)
+    sd = None if seed is None else _dev_tensor(seed, torch.float64, dev, "seed").reshape(-1)
+    if sd is not None and sd.numel() != n:
+        raise ValueError("seed must have n values")
+
+    def new(k, flag):
+        return torch.empty(k, dtype=torch.float64, device=dev) if flag else None
+
+    g, dx = new(n, want_g), new(n, want_dx)
+    dp, ds = new(1 if psh else n, want_dp), new(1 if ssh else n, want_dsigma)
+    rc = load().hf_gauss_grad_map(ctx, n, _ptr(x), _ptr(p), psh, _ptr(s), ssh, norm, _ptr(sd),
+                                  _ptr(g), _ptr(dx), _ptr(dp), _ptr(ds), _stream(dev))
+    _check(rc, ctx)
+    return g, dx, dp, ds
 
 
 @dataclass

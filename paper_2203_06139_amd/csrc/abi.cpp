@@ -4,6 +4,7 @@
 // computation runs in the HIP kernels; this file only checks and launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <map>
@@ -14,6 +15,7 @@
 #include "../../include/histfit.h"
 #include "fisher_kernels.hpp"
 #include "fit_kernels.hpp"
+#include "gradmap.hpp"
 #include "mlp.hpp"
 #include "nll_kernels.hpp"
 
@@ -24,6 +26,8 @@ static_assert(HF_NEYMAN == hf::OBJ_NEYMAN && HF_PEARSON == hf::OBJ_PEARSON &&
               "objective codes");
 static_assert(HF_U32 == hf::DT_U32 && HF_F32 == hf::DT_F32 && HF_F64 == hf::DT_F64, "dtype codes");
 static_assert(HF_ST_DOMAIN == hf::ST_DOMAIN && HF_ST_NONFINITE == hf::ST_NONFINITE, "status bits");
+static_assert(HF_NORM_LISTING == hf::GRADMAP_NORM_LISTING && HF_NORM_PDF == hf::GRADMAP_NORM_PDF,
+              "Gaussian normalisations");
 static_assert(HF_MLP_IN == hf::kMlpIn && HF_MLP_HIDDEN == hf::kMlpHidden && HF_MLP_OUT == hf::kMlpOut &&
                   HF_MLP_OUT_PAD == hf::kMlpOutPad,
               "network shape");
@@ -417,6 +421,50 @@ HF_EXPORT int hf_fisher_covariance(hf_ctx* c, int32_t B, int32_t P, int32_t obj,
   const double scale = obj == HF_POISSON ? 1.0 : 2.0;
   hipError_t e = hf::fisher_covariance(B, P, fisher, free_mask, scale, cov_out, status_out,
                                        reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return HF_OK;
+}
+
+HF_EXPORT int hf_gauss_grad_map(hf_ctx* c, int64_t n, const double* x, const double* p,
+                                int32_t p_shared, const double* sigma, int32_t sigma_shared,
+                                int32_t norm, const double* seed, double* g_out, double* dx_out,
+                                double* dp_out, double* dsigma_out, hf_stream_t stream) {
+  if (!c) return HF_EINVAL;
+  if (n < 0) return fail(c, HF_EINVAL, "n must be >= 0");
+  if (norm != HF_NORM_LISTING && norm != HF_NORM_PDF)
+    return fail(c, HF_EINVAL, "norm %d unknown", norm);
+  if ((p_shared != 0 && p_shared != 1) || (sigma_shared != 0 && sigma_shared != 1))
+    return fail(c, HF_EINVAL, "p_shared and sigma_shared must be 0 or 1");
+  const bool shared = p_shared || sigma_shared;
+  if (n == 0 && !shared) return HF_OK;
+  if ((n > 0 && !x) || (n > 0 && !p_shared && !p) || (n > 0 && !sigma_shared && !sigma))
+    return fail(c, HF_EINVAL, "x, p and sigma must be non-NULL");
+  if ((p_shared && !p) || (sigma_shared && !sigma))
+    return fail(c, HF_EINVAL, "a shared p or sigma must be non-NULL");
+  int rc = use_device(c);
+  if (rc) return rc;
+  hf::GradMapArgs a{};
+  a.n = n;
+  a.x = x;
+  a.p = p;
+  a.sigma = sigma;
+  a.seed = seed;
+  a.p_shared = p_shared;
+  a.sigma_shared = sigma_shared;
+  a.norm = norm;
+  a.g = g_out;
+  a.dx = dx_out;
+  a.dp = dp_out;
+  a.ds = dsigma_out;
+  a.part = c->part;
+  a.part_flags = c->part_flags;
+  a.ticket = c->ticket;
+  // pairs of elements as 16-byte vectors when every per-element array allows
+  bool vec = aligned16(x) && aligned16(seed) && aligned16(g_out) && aligned16(dx_out);
+  if (!p_shared) vec = vec && aligned16(p) && aligned16(dp_out);
+  if (!sigma_shared) vec = vec && aligned16(sigma) && aligned16(dsigma_out);
+  hipError_t e = hf::gauss_grad_map(a, vec, c->num_cu, kMaxGrid,
+                                    reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return HF_OK;
 }
