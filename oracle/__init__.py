@@ -95,6 +95,9 @@ def lib():
         L.or_fit_many.argtypes = [mp, ctypes.c_int, ctypes.c_int32, dp, lp, dp, dp,
                                   ctypes.POINTER(_FitOpts), dp, dp, ip, ip, ip, ctypes.c_int]
         L.or_fit_many.restype = ctypes.c_int
+        L.or_unbinned.argtypes = [mp, dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                  dp, dp, dp, dp, ip]
+        L.or_unbinned.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -213,6 +216,28 @@ def nll_grad(model: Model, objective: int, counts, theta, range4, weights=None,
     if rc != 0:
         raise ValueError("or_nll_grad failed: %d" % rc)
     return NllGrad(nll.value, grad, sc, st.value, ell)
+
+
+def unbinned(model: Model, events, lo, hi, theta, weights=None) -> NllGrad:
+    """Extended unbinned NLL  L = integral of lambda over [lo, hi] -
+    sum_e w_e ln lambda(x_e), its gradient and condition scales (Gauss +
+    polynomial models); events outside [lo, hi] are skipped."""
+    x = _f64(np.asarray(events).reshape(-1))
+    w = _f64(np.asarray(weights).reshape(-1)) if weights is not None else None
+    th = _f64(theta)
+    P = nparams(model)
+    if th.size != P:
+        raise ValueError("theta has %d values, model needs %d" % (th.size, P))
+    nll = ctypes.c_double()
+    grad = np.empty(P, dtype=np.float64)
+    sc = np.empty(P + 1, dtype=np.float64)
+    st = ctypes.c_int32()
+    m = model.c()
+    rc = lib().or_unbinned(ctypes.byref(m), _dp(x), _dp(w), x.size, float(lo), float(hi), _dp(th),
+                           ctypes.byref(nll), _dp(grad), _dp(sc), ctypes.byref(st))
+    if rc != 0:
+        raise ValueError("or_unbinned failed: %d" % rc)
+    return NllGrad(nll.value, grad, sc, st.value)
 
 
 @dataclass
