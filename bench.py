@@ -166,7 +166,7 @@ def main():
                     help="learned workload: plain fits the initialiser is trained on")
     ap.add_argument("--epochs", type=int, default=8, help="learned workload: training epochs")
     ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned", "gradient",
-                                           "fisher", "gradmap"],
+                                           "fisher", "gradmap", "unbinned"],
                     default="large1d",
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
@@ -174,7 +174,8 @@ def main():
                          "gradient: fits with the reverse-mode gradient vs central differences "
                          "for 1..4 Gaussians; fisher: the expected Hessian of the 1e7-bin "
                          "workload (and of the 2048^2 one); gradmap: the elementwise Gaussian "
-                         "gradient of 2^27 parameter sets")
+                         "gradient of 2^27 parameter sets; unbinned: the extended unbinned "
+                         "NLL + gradient of 1e7 events")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc counter CSVs of a "
                          "run with --copy-calibration (no GPU work)")
@@ -216,6 +217,8 @@ def main():
         return bench_fisher(args, hf, datagen, np, torch, dev)
     if args.workload == "gradmap":
         return bench_gradmap(args, hf, np, torch, dev)
+    if args.workload == "unbinned":
+        return bench_unbinned(args, hf, datagen, np, torch, dev)
     obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
 
@@ -484,6 +487,43 @@ def bench_gradmap(args, hf, np, torch, dev):
                         n=n, bytes_per_element=bpe),
             roofline=dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=gbs / HBM_PEAK_GBS, traffic=None))), flush=True)
+
+
+# Algorithmic FP64 flops per event of the unbinned workload (two Gaussians,
+# cubic, value + 10-component gradient), counted like FLOPS_PER_BIN: per
+# Gaussian z, z^2/2, exp, G, G z, G z^2 (6 + exp); cubic t and Horner (8) and
+# powers (3); log; reciprocal; the weighted value and 10 gradient FMAs (22).
+FLOPS_PER_EVENT = 2 * (6 + FLOPS_EXP) + 11 + FLOPS_LOG + FLOPS_DIV + 22
+
+
+def bench_unbinned(args, hf, datagen, np, torch, dev):
+    """Extended unbinned NLL + gradient of 1e7 events drawn from the 1e7-bin
+    workload's intensity (two Gaussians + cubic on [0, 100]): 8 bytes per
+    event, bound by the FP64 vector units."""
+    c = datagen.unbinned_case()
+    x = torch.as_tensor(c["events"], device=dev)
+    th = torch.as_tensor(c["theta_eval"], dtype=torch.float64, device=dev)
+    m = hf.Model.from_spec(c["spec"])
+    nll = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(m.nparams, dtype=torch.float64, device=dev)
+
+    def step(k):
+        hf.nll_unbinned(x, 0.0, 100.0, m, th, nll_out=nll, grad_out=g)
+
+    for k in range(args.warmup):
+        step(k)
+    ms = time_graph(torch, step, args.steps)
+    n = x.numel()
+    achieved = FLOPS_PER_EVENT * n / (ms * 1e-3) / 1e12
+    print(json.dumps(dict(
+        metric="events*(NLL+grad)/s", value=n / (ms * 1e-3), unit="events/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload="extended unbinned NLL + gradient, 1e7 events on [0,100], two "
+                             "Gaussians + cubic (10 parameters)", n_events=n),
+        roofline=dict(bound="alu", achieved=achieved, peak=FP64_VEC_PEAK_TFLOPS, unit="TFLOP/s",
+                      frac=achieved / FP64_VEC_PEAK_TFLOPS, traffic=None,
+                      flops_per_event=FLOPS_PER_EVENT))), flush=True)
 
 
 def fits_cpu_baseline(c, theta0, np, seconds=10.0):

@@ -301,3 +301,29 @@ def batch_case_device(seed, B, nbins=4096, device="cuda"):
     offsets = torch.arange(B + 1, dtype=torch.int64) * nbins
     ranges = torch.tensor([[0.0, 1.0]], dtype=torch.float64).repeat(B, 1)
     return counts, offsets, ranges, theta
+
+
+def unbinned_events(spec, theta, lo, hi, n_events, seed, grid=1 << 20):
+    """n_events positions drawn from the 1D intensity (as a density on
+    [lo, hi]) by inverting its cumulative integral on a fine grid: the bin
+    means of the intensity on `grid` bins give the cell probabilities, and a
+    uniform draw places each event inside its cell."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lam = np.maximum(intensity_1d(spec, np.asarray(theta, dtype=np.float64), grid, lo, hi), 0.0)
+    cdf = np.cumsum(lam)
+    cdf /= cdf[-1]
+    u = rng.random(n_events)
+    cell = np.minimum(np.searchsorted(cdf, u, side="right"), grid - 1)
+    h = (hi - lo) / grid
+    return lo + (cell + rng.random(n_events)) * h
+
+
+def unbinned_case(seed=7, n_events=10_000_000):
+    """The 1e7-bin workload's model as an intensity on [0, 100]: two
+    Gaussians + cubic, n_events positions drawn from it, evaluated at
+    theta * (1 + 0.01 N(0,1)) so that the gradient is not zero."""
+    spec = model_spec(GAUSS_POLY, 2, 3, 50.0, 50.0)
+    theta, rng = large_fit_theta(2)
+    x = unbinned_events(spec, theta, 0.0, 100.0, n_events, seed)
+    return dict(spec=spec, range=(0.0, 100.0), events=x, theta_true=theta,
+                theta_eval=perturb(theta, 0.01, np.random.Generator(np.random.PCG64(seed + 1000))))

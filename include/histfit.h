@@ -159,6 +159,30 @@ int nll_grad(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t ob
              double* grad_out, float* grad_w_out, uint32_t free_mask, int32_t* status_out,
              hf_stream_t stream);
 
+/* Extended unbinned NLL and its reverse-mode gradient: the binned
+ * objective's per-bin evaluation applied to single events at arbitrary
+ * positions (the per-event batch evaluation of RooFit-style likelihoods the
+ * paper's outlook names, sec. 5).  The HF_GAUSS_POLY model is read as an
+ * intensity lambda(x; theta) (events per unit x):
+ *   L(theta) = Lambda(theta) - sum_e w_e ln lambda(x_e),
+ *   Lambda   = integral of lambda over [lo, hi] (closed form through erf),
+ * the Poisson-process likelihood, i.e. the binned Poisson objective in the
+ * limit of single-event bins.
+ *   events     device f64[n_events], 16-byte aligned for the vector path
+ *              (any alignment works); events outside [lo, hi] are skipped.
+ *   weights    device f32[n_events] or NULL (1).
+ *   theta      device f64[P];  nll_out device f64[1], overwritten.
+ *   grad_out   device f64[P], OVERWRITTEN with dL/dtheta, or NULL for the
+ *              value alone.
+ *   status_out device i32[1] or NULL: HF_ST_DOMAIN when lambda <= 0 at an
+ *              event inside the range (L = +inf, gradient NaN),
+ *              HF_ST_NONFINITE when theta is not finite (outputs NaN).
+ * Only HF_GAUSS_POLY models (HF_EUNSUPPORTED otherwise).  Uses the
+ * context's reduction scratch: calls on one context must not overlap.     */
+int nll_unbinned(hf_ctx* ctx, const double* events, const float* weights, int64_t n_events,
+                 double lo, double hi, const hf_model* model, const double* theta,
+                 double* nll_out, double* grad_out, int32_t* status_out, hf_stream_t stream);
+
 /* Expected Hessian (Fisher information) of the objective at theta: the
  * second-derivative matrix that the paper (sec. 4) leaves to numerical
  * differentiation, in the Gauss-Newton form that parameter errors use,

@@ -134,7 +134,9 @@ def load():
                                 vp, vp]
     L.hf_fisher_covariance.argtypes = [vp, i32, i32, i32, vp, ctypes.c_uint32, vp, vp, vp]
     L.hf_gauss_grad_map.argtypes = [vp, i64, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp]
-    for fn in (L.hf_gauss_grad_map, L.hf_nll_fisher, L.hf_fisher_covariance, L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
+    L.nll_unbinned.argtypes = [vp, vp, vp, i64, ctypes.c_double, ctypes.c_double,
+                               ctypes.POINTER(HfModel), vp, vp, vp, vp, vp]
+    for fn in (L.nll_unbinned, L.hf_gauss_grad_map, L.hf_nll_fisher, L.hf_fisher_covariance, L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
                L.hf_target_to_theta, L.hf_mlp_forward, L.hf_mlp_train_step, L.hf_fit_set_tuning,
                L.hf_fit_get_tuning, L.hf_fit_max_cache_bins):
         fn.restype = ctypes.c_int
@@ -356,6 +358,32 @@ def fisher_covariance(fisher, objective=POISSON, free_mask=0, out=None, status=N
                                      _ptr(status), _stream(dev))
     _check(rc, ctx)
     return out, status
+
+
+def nll_unbinned(events, lo, hi, model: Model, theta, weights=None, want_grad=True, nll_out=None,
+                 grad_out=None, status=None):
+    """Extended unbinned NLL  Lambda - sum_e w_e ln lambda(x_e)  of the events
+    (device f64[n]) in [lo, hi] and, if want_grad, its gradient; device
+    tensors (nll, grad or None)."""
+    import torch
+    if not isinstance(events, torch.Tensor) or events.dtype != torch.float64 or events.dim() != 1:
+        raise ValueError("events must be a 1-D f64 tensor")
+    dev = events.device
+    ctx = context(dev.index)
+    ev = events.contiguous()
+    th = _dev_tensor(theta, torch.float64, dev, "theta")
+    _check_theta(th, model)
+    w = None if weights is None else _dev_tensor(weights, torch.float32, dev, "weights")
+    if w is not None and w.numel() != ev.numel():
+        raise ValueError("weights must have one value per event")
+    nll_out = torch.empty(1, dtype=torch.float64, device=dev) if nll_out is None else nll_out
+    if want_grad and grad_out is None:
+        grad_out = torch.empty(th.numel(), dtype=torch.float64, device=dev)
+    rc = load().nll_unbinned(ctx, _ptr(ev), _ptr(w), ev.numel(), float(lo), float(hi),
+                             ctypes.byref(model.c()), _ptr(th), _ptr(nll_out),
+                             _ptr(grad_out if want_grad else None), _ptr(status), _stream(dev))
+    _check(rc, ctx)
+    return nll_out, (grad_out if want_grad else None)
 
 
 def gauss_grad_map(x, p, sigma, norm=NORM_LISTING, seed=None, want_g=True, want_dx=True,

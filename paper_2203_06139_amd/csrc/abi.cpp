@@ -16,6 +16,7 @@
 #include "fisher_kernels.hpp"
 #include "fit_kernels.hpp"
 #include "gradmap.hpp"
+#include "unbinned.hpp"
 #include "mlp.hpp"
 #include "nll_kernels.hpp"
 
@@ -330,6 +331,56 @@ HF_EXPORT int nll_grad(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t o
                        hf_stream_t stream) {
   return run_objective(c, h, m, obj, prec, theta, seed, nll_out, grad_out, grad_w_out, free_mask,
                        status_out, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+HF_EXPORT int nll_unbinned(hf_ctx* c, const double* events, const float* weights,
+                           int64_t n_events, double lo, double hi, const hf_model* m,
+                           const double* theta, double* nll_out, double* grad_out,
+                           int32_t* status_out, hf_stream_t stream) {
+  if (!c) return HF_EINVAL;
+  int rc = check_model(c, m);
+  if (rc) return rc;
+  if (m->kind != HF_GAUSS_POLY)
+    return fail(c, HF_EUNSUPPORTED, "the unbinned NLL supports HF_GAUSS_POLY models only");
+  if (n_events < 0) return fail(c, HF_EINVAL, "n_events must be >= 0");
+  if (n_events > 0 && !events) return fail(c, HF_EINVAL, "events is NULL");
+  if (!(std::isfinite(lo) && std::isfinite(hi) && hi > lo))
+    return fail(c, HF_EINVAL, "range must be finite with hi > lo");
+  if (!theta) return fail(c, HF_EINVAL, "theta is NULL");
+  if (!nll_out) return fail(c, HF_EINVAL, "nll_out is NULL");
+  rc = use_device(c);
+  if (rc) return rc;
+  hf::UnbinnedFn fn = nullptr;
+  switch (m->n_gauss) {
+    case 0: fn = hf::pick_unbinned_ng0(m->poly_degree); break;
+    case 1: fn = hf::pick_unbinned_ng1(m->poly_degree); break;
+    case 2: fn = hf::pick_unbinned_ng2(m->poly_degree); break;
+    case 3: fn = hf::pick_unbinned_ng3(m->poly_degree); break;
+    case 4: fn = hf::pick_unbinned_ng4(m->poly_degree); break;
+    default: break;
+  }
+  if (!fn) return fail(c, HF_EUNSUPPORTED, "no unbinned kernel for this model");
+  hf::UnbinnedArgs a{};
+  a.x = events;
+  a.w = weights;
+  a.n = n_events;
+  a.lo = lo;
+  a.hi = hi;
+  a.theta = theta;
+  a.nll_out = nll_out;
+  a.grad_out = grad_out;
+  a.status_out = status_out;
+  a.P = nparams(m);
+  a.t_shift = m->t_shift;
+  a.t_scale = m->t_scale;
+  a.part = c->part;
+  a.part_flags = c->part_flags;
+  a.ticket = c->ticket;
+  a.log_lut = c->log_lut;
+  const bool vec = aligned16(events) && (reinterpret_cast<uintptr_t>(weights) & 7u) == 0;
+  hipError_t e = fn(a, vec, c->num_cu, kMaxGrid, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return HF_OK;
 }
 
 HF_EXPORT int hf_nll_fisher(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj,
