@@ -41,7 +41,7 @@ def build(force: bool = True) -> str:
 
 class _Model(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_gauss", ctypes.c_int32),
-                ("poly_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("poly_degree", ctypes.c_int32), ("bin_average", ctypes.c_int32),
                 ("t_shift", ctypes.c_double), ("t_scale", ctypes.c_double)]
 
 
@@ -55,15 +55,19 @@ class _FitOpts(ctypes.Structure):
 @dataclass(frozen=True)
 class Model:
     """Model descriptor: kind 1 = Gaussians + polynomial, 2 = Gaussians +
-    exponential background, 3 = 2D correlated Gaussian + constant."""
+    exponential background, 3 = 2D correlated Gaussian + constant.
+    bin_average (kind 1): mu_i is the model's average over bin i instead of
+    its value at the bin centre."""
     kind: int
     n_gauss: int = 1
     poly_degree: int = -1
     t_shift: float = 0.0
     t_scale: float = 1.0
+    bin_average: int = 0
 
     def c(self) -> _Model:
-        return _Model(self.kind, self.n_gauss, self.poly_degree, 0, self.t_shift, self.t_scale)
+        return _Model(self.kind, self.n_gauss, self.poly_degree, self.bin_average, self.t_shift,
+                      self.t_scale)
 
 
 _lib = None

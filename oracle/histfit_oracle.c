@@ -77,7 +77,7 @@ typedef struct {
   int32_t kind;
   int32_t n_gauss;
   int32_t poly_degree;
-  int32_t reserved;
+  int32_t bin_average; /* kind 1 only: 1 = mu_i is the bin average of the model */
   double t_shift;
   double t_scale;
 } or_model;
@@ -120,6 +120,7 @@ double or_neumaier_sum(const double* v, int64_t n) {
 /* ---------------------------------------------------------------------- */
 int or_nparams(const or_model* m) {
   if (!m) return -1;
+  if (m->bin_average && (m->kind != OR_GAUSS_POLY || m->poly_degree > 3)) return -1;
   switch (m->kind) {
     case OR_GAUSS_POLY:
       if (m->n_gauss < 0 || m->poly_degree < -1) return -1;
@@ -205,6 +206,45 @@ static double centre(double lo, double hi, int64_t n, int64_t i) {
   return lo + ((double)i + 0.5) * h;
 }
 
+/* Bin average of the kind-1 model over [a, b] (h = b - a): the integral of
+ * the model over the bin divided by the bin width, instead of its value at
+ * the centre.  Per Gaussian, with z_x = (x - m)/s and e_x = exp(-z_x^2/2):
+ *   mu_g   = A s sqrt(pi/2) [erf(z_b/sqrt 2) - erf(z_a/sqrt 2)] / h
+ *   dmu/dA = s sqrt(pi/2) [erf(z_b/sqrt 2) - erf(z_a/sqrt 2)] / h
+ *   dmu/dm = A (e_a - e_b) / h
+ *   dmu/ds = mu_g / s + A (z_a e_a - z_b e_b) / h
+ * Polynomial: the average of t^j over [t_c - d, t_c + d], t_c the bin
+ * centre's t and d = h / (2 t_scale), is exactly
+ *   1,  t_c,  t_c^2 + d^2/3,  t_c^3 + t_c d^2      (j = 0..3),
+ * which is also dmu/dc_j.                                                  */
+static double model1d_avg(const or_model* m, const double* th, double a, double b, double* dmu) {
+  const double h = b - a;
+  const double rt = sqrt(0.5 * 3.14159265358979323846), r2 = sqrt(2.0);
+  double mu = 0.0;
+  int k = 0;
+  for (int g = 0; g < m->n_gauss; ++g, k += 3) {
+    double A = th[k], mean = th[k + 1], s = th[k + 2];
+    double za = (a - mean) / s, zb = (b - mean) / s;
+    double ea = exp(-0.5 * za * za), eb = exp(-0.5 * zb * zb);
+    double ia = s * rt * (erf(zb / r2) - erf(za / r2)) / h;
+    double mg = A * ia;
+    mu += mg;
+    if (dmu) {
+      dmu[k] = ia;
+      dmu[k + 1] = A * (ea - eb) / h;
+      dmu[k + 2] = mg / s + A * (za * ea - zb * eb) / h;
+    }
+  }
+  double tc = (0.5 * (a + b) - m->t_shift) / m->t_scale;
+  double d = 0.5 * h / m->t_scale;
+  double avg[4] = {1.0, tc, tc * tc + d * d / 3.0, tc * tc * tc + tc * d * d};
+  for (int j = 0; j <= m->poly_degree; ++j) {
+    mu += th[k + j] * avg[j];
+    if (dmu) dmu[k + j] = avg[j];
+  }
+  return mu;
+}
+
 static double eval_mu(const or_model* m, const double* th, int64_t nx, int64_t ny,
                       const double* r, int64_t i, double* dmu) {
   if (m->kind == OR_GAUSS2D) {
@@ -212,6 +252,10 @@ static double eval_mu(const or_model* m, const double* th, int64_t nx, int64_t n
     return model2d(th, centre(r[0], r[1], nx, ix), centre(r[2], r[3], ny, iy), dmu);
   }
   (void)ny;
+  if (m->bin_average) {
+    double h = (r[1] - r[0]) / (double)nx;
+    return model1d_avg(m, th, r[0] + (double)i * h, r[0] + (double)(i + 1) * h, dmu);
+  }
   return model1d(m, th, centre(r[0], r[1], nx, i), dmu);
 }
 
