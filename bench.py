@@ -166,7 +166,7 @@ def main():
                     help="learned workload: plain fits the initialiser is trained on")
     ap.add_argument("--epochs", type=int, default=8, help="learned workload: training epochs")
     ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned", "gradient",
-                                           "fisher", "gradmap", "unbinned"],
+                                           "fisher", "gradmap", "unbinned", "binavg"],
                     default="large1d",
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
@@ -175,7 +175,8 @@ def main():
                          "for 1..4 Gaussians; fisher: the expected Hessian of the 1e7-bin "
                          "workload (and of the 2048^2 one); gradmap: the elementwise Gaussian "
                          "gradient of 2^27 parameter sets; unbinned: the extended unbinned "
-                         "NLL + gradient of 1e7 events")
+                         "NLL + gradient of 1e7 events; binavg: the 1e7-bin NLL + gradient "
+                         "with the model averaged over each bin")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc counter CSVs of a "
                          "run with --copy-calibration (no GPU work)")
@@ -219,6 +220,8 @@ def main():
         return bench_gradmap(args, hf, np, torch, dev)
     if args.workload == "unbinned":
         return bench_unbinned(args, hf, datagen, np, torch, dev)
+    if args.workload == "binavg":
+        return bench_binavg(args, hf, datagen, np, torch, dev)
     obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
 
@@ -524,6 +527,34 @@ def bench_unbinned(args, hf, datagen, np, torch, dev):
         roofline=dict(bound="alu", achieved=achieved, peak=FP64_VEC_PEAK_TFLOPS, unit="TFLOP/s",
                       frac=achieved / FP64_VEC_PEAK_TFLOPS, traffic=None,
                       flops_per_event=FLOPS_PER_EVENT))), flush=True)
+
+
+def bench_binavg(args, hf, datagen, np, torch, dev):
+    """The 1e7-bin two-Gaussian + cubic Poisson NLL + gradient with mu_i the
+    model's average over bin i (an erf and an exp per Gaussian per bin edge),
+    FP64, on one resident histogram."""
+    c = datagen.large_fit_case()
+    spec = dict(c["spec"], bin_average=1)
+    h = hf.make_hist(c["counts"], c["range"], device=dev)
+    m = hf.Model.from_spec(spec)
+    th = torch.as_tensor(c["theta_eval"], dtype=torch.float64, device=dev)
+    nll = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(m.nparams, dtype=torch.float64, device=dev)
+
+    def step(k):
+        hf.nll_grad(h, m, th, objective=hf.POISSON, nll_out=nll, grad_out=g)
+
+    for k in range(args.warmup):
+        step(k)
+    ms = time_graph(torch, step, args.steps)
+    nb = c["counts"].size
+    print(json.dumps(dict(
+        metric="bins*(NLL+grad)/s", value=nb / (ms * 1e-3), unit="bins/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload="1D histogram, 1e7 bins on [0,100], two Gaussians + cubic, model "
+                             "averaged over each bin, Poisson NLL + gradient", nbins=nb))),
+          flush=True)
 
 
 def fits_cpu_baseline(c, theta0, np, seconds=10.0):

@@ -103,7 +103,11 @@ typedef struct {
   int32_t kind;        /* hf_model_kind                                   */
   int32_t n_gauss;     /* 0..4 (HF_GAUSS2D: ignored)                      */
   int32_t poly_degree; /* -1..3 (HF_GAUSS_POLY only)                      */
-  int32_t reserved;    /* must be 0                                       */
+  int32_t bin_average; /* 0: mu_i is the model at the centre of bin i;
+                          1: its average over bin i (integral / width):
+                          erf differences per Gaussian, exact averages of
+                          t^j; HF_GAUSS_POLY with nll_eval / nll_grad in
+                          HF_FP64 only, HF_EUNSUPPORTED elsewhere         */
   double t_shift;      /* background variable t = (x - t_shift)/t_scale   */
   double t_scale;      /* nonzero                                         */
 } hf_model;

@@ -34,7 +34,7 @@ ADJOINT, FINITE_DIFF = 0, 1  # fit_batch gradient
 
 class HfModel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_gauss", ctypes.c_int32),
-                ("poly_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("poly_degree", ctypes.c_int32), ("bin_average", ctypes.c_int32),
                 ("t_shift", ctypes.c_double), ("t_scale", ctypes.c_double)]
 
 
@@ -55,21 +55,25 @@ class HfFitOpts(ctypes.Structure):
 
 @dataclass(frozen=True)
 class Model:
-    """Model descriptor (see include/histfit.h for the parameter layout)."""
+    """Model descriptor (see include/histfit.h for the parameter layout).
+    bin_average = 1 (1D Gauss + polynomial, nll_eval / nll_grad): mu_i is the
+    model's average over bin i instead of its value at the centre."""
     kind: int
     n_gauss: int = 1
     poly_degree: int = -1
     t_shift: float = 0.0
     t_scale: float = 1.0
+    bin_average: int = 0
 
     def c(self) -> HfModel:
-        return HfModel(self.kind, self.n_gauss, self.poly_degree, 0, float(self.t_shift),
-                       float(self.t_scale))
+        return HfModel(self.kind, self.n_gauss, self.poly_degree, int(self.bin_average),
+                       float(self.t_shift), float(self.t_scale))
 
     @staticmethod
     def from_spec(spec: dict) -> "Model":
         return Model(spec["kind"], spec.get("n_gauss", 1), spec.get("poly_degree", -1),
-                     spec.get("t_shift", 0.0), spec.get("t_scale", 1.0))
+                     spec.get("t_shift", 0.0), spec.get("t_scale", 1.0),
+                     spec.get("bin_average", 0))
 
     @property
     def nparams(self) -> int:

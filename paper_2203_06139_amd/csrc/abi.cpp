@@ -18,6 +18,7 @@
 #include "gradmap.hpp"
 #include "unbinned.hpp"
 #include "mlp.hpp"
+#include "nll_avg.hpp"
 #include "nll_kernels.hpp"
 
 #define HF_EXPORT extern "C" __attribute__((visibility("default")))
@@ -90,9 +91,15 @@ int use_device(hf_ctx* c) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-int check_model(hf_ctx* c, const hf_model* m) {
+// allow_avg: the caller evaluates bin-average models (nll_eval, nll_grad).
+int check_model(hf_ctx* c, const hf_model* m, bool allow_avg = false) {
   if (!m) return fail(c, HF_EINVAL, "model is NULL");
-  if (m->reserved != 0) return fail(c, HF_EINVAL, "model.reserved must be 0");
+  if (m->bin_average != 0 && m->bin_average != 1)
+    return fail(c, HF_EINVAL, "model.bin_average must be 0 or 1");
+  if (m->bin_average && m->kind != HF_GAUSS_POLY)
+    return fail(c, HF_EUNSUPPORTED, "bin-average models are HF_GAUSS_POLY only");
+  if (m->bin_average && !allow_avg)
+    return fail(c, HF_EUNSUPPORTED, "this call does not take bin-average models");
   switch (m->kind) {
     case HF_GAUSS_POLY:
       if (m->n_gauss < 0 || m->n_gauss > 4)
@@ -191,7 +198,7 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
                   float* grad_w_out, uint32_t free_mask, int32_t* status_out, hipStream_t stream,
                   bool grad) {
   if (!c) return HF_EINVAL;
-  int rc = check_model(c, m);
+  int rc = check_model(c, m, true);
   if (rc) return rc;
   const bool two_d = m->kind == HF_GAUSS2D;
   rc = check_hist(c, h, two_d);
@@ -199,6 +206,9 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   if (obj < HF_NEYMAN || obj > HF_POISSON) return fail(c, HF_EINVAL, "objective %d unknown", obj);
   if (prec != HF_FP64 && prec != HF_FP32_BIN)
     return fail(c, HF_EINVAL, "precision %d unknown", prec);
+  const bool avg = m->bin_average != 0;
+  if (avg && prec != HF_FP64)
+    return fail(c, HF_EUNSUPPORTED, "bin-average models are evaluated in HF_FP64 only");
   if (!theta) return fail(c, HF_EINVAL, "theta is NULL");
   if (!nll_out) return fail(c, HF_EINVAL, "nll_out is NULL");
   if (grad && !grad_out) return fail(c, HF_EINVAL, "grad_out is NULL");
@@ -207,8 +217,21 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   rc = use_device(c);
   if (rc) return rc;
 
-  hf::LaunchFn fn = two_d ? hf::pick_2d(obj, grad, prec == HF_FP32_BIN)
-                          : pick_1d(m->n_gauss, bkg_code(m), obj, grad, prec == HF_FP32_BIN);
+  hf::LaunchFn fn = nullptr;
+  if (two_d) {
+    fn = hf::pick_2d(obj, grad, prec == HF_FP32_BIN);
+  } else if (avg) {
+    switch (m->n_gauss) {
+      case 0: fn = hf::pick_avg_ng0(m->poly_degree, obj, grad); break;
+      case 1: fn = hf::pick_avg_ng1(m->poly_degree, obj, grad); break;
+      case 2: fn = hf::pick_avg_ng2(m->poly_degree, obj, grad); break;
+      case 3: fn = hf::pick_avg_ng3(m->poly_degree, obj, grad); break;
+      case 4: fn = hf::pick_avg_ng4(m->poly_degree, obj, grad); break;
+      default: break;
+    }
+  } else {
+    fn = pick_1d(m->n_gauss, bkg_code(m), obj, grad, prec == HF_FP32_BIN);
+  }
   if (!fn) return fail(c, HF_EUNSUPPORTED, "no kernel for this model");
 
   hf::NllArgs a{};
@@ -219,7 +242,8 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   a.dtype = h->counts_dtype;
   a.obj = obj;
   a.hx = (h->xhi - h->xlo) / static_cast<double>(h->nx);
-  a.x0 = h->xlo + 0.5 * a.hx;
+  // the bin-average kernels take the left edge of bin 0, the others its centre
+  a.x0 = avg ? h->xlo : h->xlo + 0.5 * a.hx;
   if (two_d) {
     a.hy = (h->yhi - h->ylo) / static_cast<double>(h->ny);
     a.y0 = h->ylo + 0.5 * a.hy;
@@ -253,8 +277,9 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   // 2D work items are 16-bin pieces of one row (a row's tail is a short piece)
   const int64_t items_bins =
       two_d ? ((a.nx + hf::kChunk2D - 1) / hf::kChunk2D) * hf::kChunk2D * a.ny : a.nx;
-  const int grid = objective_grid(c, items_bins,
-                                  two_d ? hf::kChunk2D : hf::chunk_bins(m->n_gauss), per_cu);
+  const int grid = objective_grid(
+      c, items_bins, two_d ? hf::kChunk2D : (avg ? hf::kAvgChunk : hf::chunk_bins(m->n_gauss)),
+      per_cu);
   hipError_t e = fn(a, grid, stream, nullptr);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return HF_OK;
@@ -313,7 +338,7 @@ HF_EXPORT void hf_ctx_destroy(hf_ctx* c) {
 HF_EXPORT const char* hf_last_error(const hf_ctx* c) { return c ? c->err.c_str() : ""; }
 
 HF_EXPORT int hf_model_nparams(const hf_model* m) {
-  const int rc = check_model(nullptr, m);
+  const int rc = check_model(nullptr, m, true);
   if (rc) return rc;
   return nparams(m);
 }

@@ -1,0 +1,180 @@
+// nll_avg.hpp -- objective (+ gradient) kernels of the bin-average 1D model:
+// mu_i is the Gauss + polynomial model's integral over bin i divided by the
+// bin width, instead of its value at the bin centre (the "integral of the
+// function in the bin" form of a binned fit).
+//
+// Per Gaussian, with edges a < b of the bin, z_x = (x - m)/s and
+// e_x = exp(-z_x^2/2):
+//   mu_g   = A s sqrt(pi/2) [erf(z_b/sqrt 2) - erf(z_a/sqrt 2)] / h
+//   dmu/dA = s sqrt(pi/2) [erf difference] / h
+//   dmu/dm = A (e_a - e_b) / h
+//   dmu/ds = mu_g / s + A (z_a e_a - z_b e_b) / h
+// and for the polynomial in t the exact bin averages of t^j
+//   1, t_c, t_c^2 + d^2/3, t_c^3 + t_c d^2   (d = h / (2 t_scale)).
+// A thread walks a chunk of consecutive bins edge to edge: each bin
+// evaluates erf and exp at its right edge and hands them to the next bin, so
+// a bin costs one erf and one exp per Gaussian.  The objective terms, the
+// reverse sweep (w ubar times the partials above) and the reduction are the
+// centre model's.  FP64 only.
+#pragma once
+
+#include "chunk.hpp"
+#include "nll_kernels.hpp"
+
+namespace hf {
+
+// Bins per thread per step of the bin-average kernel.
+constexpr int kAvgChunk = 8;
+
+struct UnitFactors {
+  __device__ __forceinline__ double final_factor(int) const { return 1.0; }
+};
+
+// a.x0 holds the left edge of bin 0 (not its centre) for these kernels.
+template <int NG, int DEG, int OBJ, bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
+  using S = Shape1D<NG, DEG>;
+  constexpr int P = S::P;
+  constexpr int NV = GRAD ? P + 1 : 1;
+  constexpr int G1 = NG > 0 ? NG : 1;
+  constexpr double kRt = 1.2533141373155002512;   // sqrt(pi/2)
+  constexpr double kIr2 = 0.70710678118654752440;  // 1/sqrt(2)
+  __shared__ double2 lut[OBJ == OBJ_POISSON ? kLogLut : 1];
+  if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
+  Model1D<NG, DEG> M;
+  M.init(a.theta, a.t_shift, a.t_scale);
+  double sg[G1];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) sg[g] = a.theta[3 * g + 2];
+  const double invh = 1.0 / a.hx;
+  const double d = 0.5 * a.hx * M.ta;
+  const double d2 = d * d;
+  if constexpr (OBJ == OBJ_POISSON) __syncthreads();
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  int flags = 0;
+  const double gseed = a.seed ? a.seed[0] : 1.0;
+  const double seed = a.grad_w_out ? gseed : 1.0;
+  const bool finite = all_finite(a.theta, a.P);
+  const int64_t nb = a.nx;
+  const int64_t nch = (nb + kAvgChunk - 1) / kAvgChunk;
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t c = tid; c < nch; c += stride) {
+    const int64_t i0 = c * kAvgChunk;
+    const int len = static_cast<int>(nb - i0 < kAvgChunk ? nb - i0 : kAvgChunk);
+    // left edge of the chunk's first bin
+    double za[G1], Ea[G1], ea[G1];
+    {
+      const double x = fma(static_cast<double>(i0), a.hx, a.x0);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        za[g] = (x - M.m[g]) * M.is[g];
+        Ea[g] = erf(za[g] * kIr2);
+        ea[g] = exp_fast(-0.5 * za[g] * za[g]);
+      }
+    }
+    for (int k = 0; k < len; ++k) {
+      const int64_t i = i0 + k;
+      const double xb = fma(static_cast<double>(i + 1), a.hx, a.x0);
+      double mu = 0.0;
+      double J[P];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const double zb = (xb - M.m[g]) * M.is[g];
+        const double Eb = erf(zb * kIr2);
+        const double eb = exp_fast(-0.5 * zb * zb);
+        const double ia = sg[g] * kRt * (Eb - Ea[g]) * invh;
+        const double mg = M.A[g] * ia;
+        mu += mg;
+        if constexpr (GRAD) {
+          J[3 * g] = ia;
+          J[3 * g + 1] = M.A[g] * (ea[g] - eb) * invh;
+          J[3 * g + 2] = fma(mg, M.is[g], M.A[g] * fma(za[g], ea[g], -zb * eb) * invh);
+        }
+        za[g] = zb;
+        Ea[g] = Eb;
+        ea[g] = eb;
+      }
+      if constexpr (S::NB > 0) {
+        const double xc = fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
+        const double tc = (xc - M.tshift) * M.ta;
+        double avg[4];
+        avg[0] = 1.0;
+        avg[1] = tc;
+        avg[2] = fma(tc, tc, d2 * (1.0 / 3.0));
+        avg[3] = tc * fma(tc, tc, d2);
+#pragma unroll
+        for (int j = 0; j < S::NB; ++j) {
+          mu = fma(M.c[j], avg[j], mu);
+          if constexpr (GRAD) J[3 * NG + j] = avg[j];
+        }
+      }
+      const double n = load_count1(a, i);
+      const double w = a.weights ? static_cast<double>(a.weights[i]) : 1.0;
+      double l, ub;
+      flags |= objective_t<OBJ, false>(n, mu, lut, l, ub) ? ST_DOMAIN : 0;
+      acc[0] = fma(w, l, acc[0]);
+      if constexpr (GRAD) {
+        const double mb = w * ub;
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[1 + p] = fma(mb, J[p], acc[1 + p]);
+      }
+      if (a.grad_w_out) a.grad_w_out[i] = static_cast<float>(seed * l);
+    }
+  }
+  __shared__ double tot[NV];
+  __shared__ int totf;
+  if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
+    write_outputs<NV>(a, UnitFactors{}, tot, totf, finite, gseed);
+}
+
+template <int NG, int DEG, int OBJ, bool GRAD>
+hipError_t launch_1d_avg(const NllArgs& a, int grid, hipStream_t s, int* occ) {
+  return launch_or_occupancy(k_nll_1d_avg<NG, DEG, OBJ, GRAD>, a, grid, s, occ);
+}
+
+template <int NG, int DEG>
+LaunchFn pick_avg_obj(int obj, bool grad) {
+  switch (obj) {
+    case OBJ_NEYMAN:
+      return grad ? &launch_1d_avg<NG, DEG, OBJ_NEYMAN, true> : &launch_1d_avg<NG, DEG, OBJ_NEYMAN, false>;
+    case OBJ_PEARSON:
+      return grad ? &launch_1d_avg<NG, DEG, OBJ_PEARSON, true>
+                  : &launch_1d_avg<NG, DEG, OBJ_PEARSON, false>;
+    case OBJ_POISSON:
+      return grad ? &launch_1d_avg<NG, DEG, OBJ_POISSON, true>
+                  : &launch_1d_avg<NG, DEG, OBJ_POISSON, false>;
+    default:
+      return nullptr;
+  }
+}
+
+template <int NG>
+LaunchFn pick_avg_ng(int degree, int obj, bool grad) {
+  switch (degree) {
+    case -1:
+      if constexpr (NG == 0) return nullptr;
+      else return pick_avg_obj<NG, BKG_NONE>(obj, grad);
+    case 0:
+      return pick_avg_obj<NG, 0>(obj, grad);
+    case 1:
+      return pick_avg_obj<NG, 1>(obj, grad);
+    case 2:
+      return pick_avg_obj<NG, 2>(obj, grad);
+    case 3:
+      return pick_avg_obj<NG, 3>(obj, grad);
+    default:
+      return nullptr;
+  }
+}
+
+// Defined in nll1d_avg_ng{0..4}.hip.
+LaunchFn pick_avg_ng0(int degree, int obj, bool grad);
+LaunchFn pick_avg_ng1(int degree, int obj, bool grad);
+LaunchFn pick_avg_ng2(int degree, int obj, bool grad);
+LaunchFn pick_avg_ng3(int degree, int obj, bool grad);
+LaunchFn pick_avg_ng4(int degree, int obj, bool grad);
+
+}  // namespace hf
