@@ -74,3 +74,21 @@ def test_null_arguments_rejected_without_gpu(lib):
                          None, None, None) == -1
     assert lib.hf_last_error(None) == b""
     assert lib.hf_ctx_create(None, 0) == -1
+
+
+def test_newer_entry_points_reject_null_context_without_gpu(lib):
+    assert lib.hf_nll_fisher(None, None, None, 2, None, None, None, None) == -1
+    assert lib.hf_fisher_covariance(None, 1, 5, 2, None, 0, None, None, None) == -1
+    assert lib.hf_gauss_grad_map(None, 4, None, None, 0, None, 0, 0, None, None, None, None, None,
+                                 None) == -1
+    assert lib.nll_unbinned(None, None, None, 4, 0.0, 1.0, None, None, None, None, None,
+                            None) == -1
+
+
+def test_bin_average_flag_is_validated_on_the_host(lib):
+    import paper_2203_06139_amd as hf
+    assert hf.Model(hf.GAUSS_POLY, 2, 3, 50, 50, bin_average=1).nparams == 10
+    m = hf.HfModel(hf.GAUSS_EXP, 1, -1, 1, 0.0, 1.0)  # bin average of the exponential model
+    assert lib.hf_model_nparams(ctypes.byref(m)) == -2
+    m = hf.HfModel(hf.GAUSS_POLY, 1, 1, 2, 0.0, 1.0)  # flag must be 0 or 1
+    assert lib.hf_model_nparams(ctypes.byref(m)) == -1
