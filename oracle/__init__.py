@@ -99,6 +99,9 @@ def lib():
         L.or_fit_many.argtypes = [mp, ctypes.c_int, ctypes.c_int32, dp, lp, dp, dp,
                                   ctypes.POINTER(_FitOpts), dp, dp, ip, ip, ip, ctypes.c_int]
         L.or_fit_many.restype = ctypes.c_int
+        L.or_nll_grad_edges.argtypes = [mp, ctypes.c_int, dp, dp, ctypes.c_int64, dp, dp, dp, dp,
+                                        dp, dp, ip, ctypes.c_int]
+        L.or_nll_grad_edges.restype = ctypes.c_int
         L.or_unbinned.argtypes = [mp, dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                   dp, dp, dp, dp, ip]
         L.or_unbinned.restype = ctypes.c_int
@@ -219,6 +222,31 @@ def nll_grad(model: Model, objective: int, counts, theta, range4, weights=None,
                               nthreads)
     if rc != 0:
         raise ValueError("or_nll_grad failed: %d" % rc)
+    return NllGrad(nll.value, grad, sc, st.value, ell)
+
+
+def nll_grad_edges(model: Model, objective: int, counts, edges, theta, weights=None,
+                   want_ell: bool = False, nthreads: int = 1) -> NllGrad:
+    """NLL, gradient and condition scales of a 1D histogram whose bin i spans
+    [edges[i], edges[i+1]] (bins of any widths)."""
+    c = _f64(np.asarray(counts).reshape(-1))
+    e = _f64(np.asarray(edges).reshape(-1))
+    if e.size != c.size + 1:
+        raise ValueError("edges must have nbins + 1 values")
+    w = _f64(np.asarray(weights).reshape(-1)) if weights is not None else None
+    th = _f64(theta)
+    P = nparams(model)
+    nll = ctypes.c_double()
+    grad = np.empty(P, dtype=np.float64)
+    sc = np.empty(P + 1, dtype=np.float64)
+    ell = np.empty(c.size, dtype=np.float64) if want_ell else None
+    st = ctypes.c_int32()
+    m = model.c()
+    rc = lib().or_nll_grad_edges(ctypes.byref(m), objective, _dp(c), _dp(w), c.size, _dp(e),
+                                 _dp(th), ctypes.byref(nll), _dp(grad), _dp(sc), _dp(ell),
+                                 ctypes.byref(st), nthreads)
+    if rc != 0:
+        raise ValueError("or_nll_grad_edges failed: %d" % rc)
     return NllGrad(nll.value, grad, sc, st.value, ell)
 
 

@@ -245,13 +245,20 @@ static double model1d_avg(const or_model* m, const double* th, double a, double 
   return mu;
 }
 
+/* mu of bin i.  edges (1D, nullable): the nx + 1 bin edges of a histogram
+ * with bins of any widths; bin i spans [edges[i], edges[i+1]] and its
+ * centre is their midpoint.  Without edges the bins are uniform on r.     */
 static double eval_mu(const or_model* m, const double* th, int64_t nx, int64_t ny,
-                      const double* r, int64_t i, double* dmu) {
+                      const double* r, const double* edges, int64_t i, double* dmu) {
   if (m->kind == OR_GAUSS2D) {
     int64_t ix = i % nx, iy = i / nx;
     return model2d(th, centre(r[0], r[1], nx, ix), centre(r[2], r[3], ny, iy), dmu);
   }
   (void)ny;
+  if (edges) {
+    if (m->bin_average) return model1d_avg(m, th, edges[i], edges[i + 1], dmu);
+    return model1d(m, th, 0.5 * (edges[i] + edges[i + 1]), dmu);
+  }
   if (m->bin_average) {
     double h = (r[1] - r[0]) / (double)nx;
     return model1d_avg(m, th, r[0] + (double)i * h, r[0] + (double)(i + 1) * h, dmu);
@@ -262,7 +269,7 @@ static double eval_mu(const or_model* m, const double* th, int64_t nx, int64_t n
 int or_model_eval(const or_model* m, const double* th, int64_t nx, int64_t ny,
                   const double* range4, double* mu_out) {
   if (or_nparams(m) < 0 || nx <= 0 || ny <= 0 || !th || !range4 || !mu_out) return -1;
-  for (int64_t i = 0; i < nx * ny; ++i) mu_out[i] = eval_mu(m, th, nx, ny, range4, i, NULL);
+  for (int64_t i = 0; i < nx * ny; ++i) mu_out[i] = eval_mu(m, th, nx, ny, range4, NULL, i, NULL);
   return 0;
 }
 
@@ -316,6 +323,7 @@ typedef struct {
   const double* weights;
   int64_t nx, ny;
   const double* range;
+  const double* edges;
   const double* th;
   int P;
   int64_t begin, end;
@@ -337,7 +345,8 @@ static void run_chunk(chunk_job* j) {
   for (int64_t i = j->begin; i < j->end; ++i) {
     double n = j->counts[i];
     double w = j->weights ? j->weights[i] : 1.0;
-    double mu = eval_mu(j->m, j->th, j->nx, j->ny, j->range, i, j->want_grad ? dmu : NULL);
+    double mu = eval_mu(j->m, j->th, j->nx, j->ny, j->range, j->edges, i,
+                        j->want_grad ? dmu : NULL);
     double l, ubar;
     int rc = objective_term(j->obj, n, mu, &l, &ubar);
     if (rc == 1) j->status |= OR_ST_DOMAIN;
@@ -370,10 +379,10 @@ static int theta_finite(const double* th, int P) {
  * nx*ny values) receives the unweighted per-bin terms l_i.  nthreads > 1
  * splits the bins into nthreads contiguous chunks, each summed as above,
  * and combines the chunk sums in chunk order.                            */
-int or_nll_grad_mt(const or_model* m, int obj, const double* counts, const double* weights,
-                   int64_t nx, int64_t ny, const double* range4, const double* theta,
-                   double* nll_out, double* grad_out, double* scale_out, double* ell_out,
-                   int32_t* status_out, int nthreads) {
+static int nll_grad_impl(const or_model* m, int obj, const double* counts, const double* weights,
+                         int64_t nx, int64_t ny, const double* range4, const double* edges,
+                         const double* theta, double* nll_out, double* grad_out,
+                         double* scale_out, double* ell_out, int32_t* status_out, int nthreads) {
   int P = or_nparams(m);
   if (P < 0 || P > OR_MAXP) return -2;
   if (!counts || !range4 || !theta || !nll_out || nx <= 0 || ny <= 0) return -1;
@@ -399,6 +408,7 @@ int or_nll_grad_mt(const or_model* m, int obj, const double* counts, const doubl
     j->nx = nx;
     j->ny = ny;
     j->range = range4;
+    j->edges = edges;
     j->th = theta;
     j->P = P;
     j->begin = nb * t / nthreads;
@@ -443,6 +453,29 @@ int or_nll_grad_mt(const or_model* m, int obj, const double* counts, const doubl
   }
   if (status_out) *status_out = status;
   return 0;
+}
+
+int or_nll_grad_mt(const or_model* m, int obj, const double* counts, const double* weights,
+                   int64_t nx, int64_t ny, const double* range4, const double* theta,
+                   double* nll_out, double* grad_out, double* scale_out, double* ell_out,
+                   int32_t* status_out, int nthreads) {
+  return nll_grad_impl(m, obj, counts, weights, nx, ny, range4, NULL, theta, nll_out, grad_out,
+                       scale_out, ell_out, status_out, nthreads);
+}
+
+/* As or_nll_grad_mt for a 1D histogram with bins of any widths: bin i spans
+ * [edges[i], edges[i+1]] (nx + 1 ascending edges); the model is taken at
+ * the midpoint, or averaged over the bin for bin-average models.          */
+int or_nll_grad_edges(const or_model* m, int obj, const double* counts, const double* weights,
+                      int64_t nx, const double* edges, const double* theta, double* nll_out,
+                      double* grad_out, double* scale_out, double* ell_out, int32_t* status_out,
+                      int nthreads) {
+  if (!edges || nx <= 0 || m->kind == OR_GAUSS2D) return -1;
+  for (int64_t i = 0; i < nx; ++i)
+    if (!(edges[i + 1] > edges[i])) return -1;
+  double r[4] = {edges[0], edges[nx], 0.0, 1.0};
+  return nll_grad_impl(m, obj, counts, weights, nx, 1, r, edges, theta, nll_out, grad_out,
+                       scale_out, ell_out, status_out, nthreads);
 }
 
 int or_nll_grad(const or_model* m, int obj, const double* counts, const double* weights,
@@ -584,7 +617,7 @@ int or_fisher(const or_model* m, int obj, const double* counts, const double* we
   for (int64_t i = 0; i < nx * ny; ++i) {
     double n = counts[i];
     double w = weights ? weights[i] : 1.0;
-    double mu = eval_mu(m, theta, nx, ny, range4, i, dmu);
+    double mu = eval_mu(m, theta, nx, ny, range4, NULL, i, dmu);
     double c;
     if (obj == OR_POISSON) c = 1.0 / mu;
     else if (obj == OR_PEARSON) c = 2.0 / mu;

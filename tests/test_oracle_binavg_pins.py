@@ -101,3 +101,70 @@ def test_polynomial_average_closed_form(orc):
             a, b = -2.0 + 2 * i, -2.0 + 2 * (i + 1)
             q, _ = integrate.quad(lambda x: ((x - T_SHIFT) / T_SCALE) ** deg, a, b, epsrel=1e-14)
             assert mu[i] == pytest.approx(q / 2.0, rel=1e-13, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Bins of any widths (explicit edges)
+# ---------------------------------------------------------------------------
+def _edges(lo, hi, nb, seed):
+    """Ascending edges with widths varying over two orders of magnitude."""
+    w = np.exp(np.random.default_rng(seed).uniform(np.log(0.01), np.log(1.0), nb))
+    e = np.concatenate([[0.0], np.cumsum(w)])
+    return lo + (hi - lo) * e / e[-1]
+
+
+def _mu_from_ell(orc, M, edges, th):
+    # Poisson with n = 0 gives l_i = mu_i exactly
+    return orc.nll_grad_edges(M, 2, np.zeros(edges.size - 1), edges, th, want_ell=True).ell
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_edges_centre_and_average_values(orc, case):
+    ng, deg, th, r, nb = CASES[case]
+    e = _edges(r[0], r[1], nb, seed=case)
+    centre = orc.Model(1, ng, deg, T_SHIFT, T_SCALE)
+    mu_c = _mu_from_ell(orc, centre, e, th)
+    mid = 0.5 * (e[:-1] + e[1:])
+    np.testing.assert_allclose(mu_c, np_f(np.array(th), mid, ng, deg), rtol=1e-13,
+                               atol=1e-13 * np.max(np.abs(mu_c)))
+    mu_a = _mu_from_ell(orc, _model(orc, ng, deg), e, th)
+    for i in range(nb):
+        q, _ = integrate.quad(lambda x: float(np_f(np.array(th), np.array([x]), ng, deg)[0]),
+                              e[i], e[i + 1], epsabs=0, epsrel=1e-13, limit=200)
+        assert mu_a[i] == pytest.approx(q / (e[i + 1] - e[i]), rel=1e-10,
+                                        abs=1e-11 * np.max(np.abs(mu_a))), i
+
+
+@pytest.mark.parametrize("avg", [0, 1])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_edges_gradient_by_complex_step(orc, case, avg):
+    ng, deg, th, r, nb = CASES[case]
+    e = _edges(r[0], r[1], nb, seed=10 + case)
+    M = orc.Model(1, ng, deg, T_SHIFT, T_SCALE, bin_average=avg)
+    mu = _mu_from_ell(orc, M, e, th)
+    n = np.random.default_rng(case).poisson(np.maximum(mu, 0.5)).astype(np.float64)
+    ref = orc.nll_grad_edges(M, 2, n, e, th)
+
+    def L(tc):
+        m = (np_avg(tc, e[:-1] + 0j, e[1:] + 0j, ng, deg) if avg else
+             np_f(tc, 0.5 * (e[:-1] + e[1:]) + 0j, ng, deg))
+        return np.sum(m - n + np.where(n > 0, n * np.log(np.where(n > 0, n, 1) / m), 0))
+
+    assert ref.nll == pytest.approx(float(np.real(L(np.array(th, dtype=complex)))), rel=1e-12)
+    for k in range(len(th)):
+        tc = np.array(th, dtype=complex)
+        tc[k] += 1j * 1e-30
+        cs = np.imag(L(tc)) / 1e-30
+        assert abs(ref.grad[k] - cs) <= 1e-11 * ref.scales[1 + k], (k, ref.grad[k], cs)
+
+
+def test_uniform_edges_reproduce_the_range_form(orc):
+    ng, deg, th, r, nb = CASES[1]
+    n = np.random.default_rng(2).poisson(30, nb).astype(np.float64)
+    e = np.linspace(r[0], r[1], nb + 1)
+    for avg in (0, 1):
+        M = orc.Model(1, ng, deg, T_SHIFT, T_SCALE, bin_average=avg)
+        a = orc.nll_grad_edges(M, 1, n, e, th)
+        b = orc.nll_grad(M, 1, n, th, r)
+        assert abs(a.nll - b.nll) <= 1e-13 * b.scales[0]
+        assert np.all(np.abs(a.grad - b.grad) <= 1e-13 * b.scales[1:])
