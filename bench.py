@@ -166,7 +166,7 @@ def main():
                     help="learned workload: plain fits the initialiser is trained on")
     ap.add_argument("--epochs", type=int, default=8, help="learned workload: training epochs")
     ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned", "gradient",
-                                           "fisher", "gradmap", "unbinned", "binavg"],
+                                           "fisher", "gradmap", "unbinned", "binavg", "edges"],
                     default="large1d",
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
@@ -176,7 +176,8 @@ def main():
                          "workload (and of the 2048^2 one); gradmap: the elementwise Gaussian "
                          "gradient of 2^27 parameter sets; unbinned: the extended unbinned "
                          "NLL + gradient of 1e7 events; binavg: the 1e7-bin NLL + gradient "
-                         "with the model averaged over each bin")
+                         "with the model averaged over each bin; edges: the same on 1e7 bins "
+                         "of varying widths")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc counter CSVs of a "
                          "run with --copy-calibration (no GPU work)")
@@ -222,6 +223,8 @@ def main():
         return bench_unbinned(args, hf, datagen, np, torch, dev)
     if args.workload == "binavg":
         return bench_binavg(args, hf, datagen, np, torch, dev)
+    if args.workload == "edges":
+        return bench_binavg(args, hf, datagen, np, torch, dev, edges=True)
     obj = {"poisson": hf.POISSON, "neyman": hf.NEYMAN, "pearson": hf.PEARSON}[args.objective]
     prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
 
@@ -529,13 +532,20 @@ def bench_unbinned(args, hf, datagen, np, torch, dev):
                       flops_per_event=FLOPS_PER_EVENT))), flush=True)
 
 
-def bench_binavg(args, hf, datagen, np, torch, dev):
+def bench_binavg(args, hf, datagen, np, torch, dev, edges=False):
     """The 1e7-bin two-Gaussian + cubic Poisson NLL + gradient with mu_i the
     model's average over bin i (an erf and an exp per Gaussian per bin edge),
-    FP64, on one resident histogram."""
+    FP64, on one resident histogram; with edges, the centre model on 1e7 bins
+    whose widths vary 100-fold (8 more bytes per bin, one exp per Gaussian
+    per bin)."""
     c = datagen.large_fit_case()
-    spec = dict(c["spec"], bin_average=1)
-    h = hf.make_hist(c["counts"], c["range"], device=dev)
+    spec = dict(c["spec"], bin_average=0 if edges else 1)
+    e = None
+    if edges:
+        w = np.exp(np.random.default_rng(8).uniform(np.log(0.01), np.log(1.0), c["nbins"]))
+        e = np.concatenate([[0.0], np.cumsum(w)])
+        e = 100.0 * e / e[-1]
+    h = hf.make_hist(c["counts"], c["range"], device=dev, edges=e)
     m = hf.Model.from_spec(spec)
     th = torch.as_tensor(c["theta_eval"], dtype=torch.float64, device=dev)
     nll = torch.empty(1, dtype=torch.float64, device=dev)
@@ -552,8 +562,10 @@ def bench_binavg(args, hf, datagen, np, torch, dev):
         metric="bins*(NLL+grad)/s", value=nb / (ms * 1e-3), unit="bins/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
-        config=dict(workload="1D histogram, 1e7 bins on [0,100], two Gaussians + cubic, model "
-                             "averaged over each bin, Poisson NLL + gradient", nbins=nb))),
+        config=dict(workload=("1D histogram, 1e7 bins of varying widths on [0,100], two "
+                              "Gaussians + cubic at the bin midpoints" if edges else
+                              "1D histogram, 1e7 bins on [0,100], two Gaussians + cubic, model "
+                              "averaged over each bin") + ", Poisson NLL + gradient", nbins=nb))),
           flush=True)
 
 

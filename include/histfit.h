@@ -121,8 +121,16 @@ typedef struct {
   int64_t ny;           /* bins along y; 1 for the 1D models               */
   int32_t counts_dtype; /* hf_dtype                                        */
   int32_t reserved;     /* must be 0                                       */
-  double xlo, xhi;      /* x range, xhi > xlo                              */
+  double xlo, xhi;      /* x range, xhi > xlo (ignored with x_edges)       */
   double ylo, yhi;      /* y range (2D only), yhi > ylo                    */
+  const double* x_edges; /* NULL: nx uniform bins on [xlo, xhi].  Else
+                           device f64[nx + 1], ascending: 1D bins of any
+                           widths, bin i spanning [x_edges[i],
+                           x_edges[i+1]]; the model is taken at the bin's
+                           midpoint, or averaged over it (bin_average).
+                           nll_eval / nll_grad in HF_FP64 only; edges that
+                           are not ascending give undefined values (never
+                           an out-of-bounds access).                      */
 } hf_hist;
 
 /* Creates a context on HIP device `device` and makes it current for the

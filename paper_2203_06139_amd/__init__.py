@@ -43,7 +43,8 @@ class HfHist(ctypes.Structure):
                 ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("counts_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("xlo", ctypes.c_double), ("xhi", ctypes.c_double),
-                ("ylo", ctypes.c_double), ("yhi", ctypes.c_double)]
+                ("ylo", ctypes.c_double), ("yhi", ctypes.c_double),
+                ("x_edges", ctypes.c_void_p)]
 
 
 class HfFitOpts(ctypes.Structure):
@@ -228,11 +229,14 @@ def _check_offsets(offsets, n_counts):
 
 @dataclass
 class Hist:
-    """A histogram on the device: counts [nx] or [ny, nx] (x fastest)."""
+    """A histogram on the device: counts [nx] or [ny, nx] (x fastest);
+    edges: None (uniform bins on xrange) or a device f64[nx + 1] of ascending
+    bin edges (1D bins of any widths)."""
     counts: object
     xrange: tuple
     yrange: tuple = (0.0, 1.0)
     weights: object = None
+    edges: object = None
 
     def c(self) -> HfHist:
         c = self.counts
@@ -240,11 +244,13 @@ class Hist:
         ny = c.shape[0] if c.dim() == 2 else 1
         return HfHist(c.data_ptr(), self.weights.data_ptr() if self.weights is not None else None,
                       nx, ny, _dtype_code(c), 0, float(self.xrange[0]), float(self.xrange[1]),
-                      float(self.yrange[0]), float(self.yrange[1]))
+                      float(self.yrange[0]), float(self.yrange[1]),
+                      self.edges.data_ptr() if self.edges is not None else None)
 
 
-def make_hist(counts, xrange, yrange=(0.0, 1.0), weights=None, device=None) -> Hist:
-    """Device copies (if needed) of counts and weights, contiguous."""
+def make_hist(counts, xrange, yrange=(0.0, 1.0), weights=None, device=None, edges=None) -> Hist:
+    """Device copies (if needed) of counts, weights and bin edges, contiguous.
+    With edges (nx + 1 ascending values) xrange is taken from its ends."""
     import numpy as np
     import torch
     device = device or torch.device("cuda", torch.cuda.current_device())
@@ -259,7 +265,14 @@ def make_hist(counts, xrange, yrange=(0.0, 1.0), weights=None, device=None) -> H
         c = c.to(torch.float64)
     c = c.to(device).contiguous()
     w = None if weights is None else _dev_tensor(weights, torch.float32, device, "weights")
-    return Hist(c, tuple(xrange), tuple(yrange), w)
+    e = None
+    if edges is not None:
+        e = _dev_tensor(edges, torch.float64, device, "edges").reshape(-1)
+        if c.dim() != 1 or e.numel() != c.numel() + 1:
+            raise ValueError("edges must have nx + 1 values for a 1D histogram")
+        ends = e[[0, -1]].cpu().tolist()
+        xrange = (ends[0], ends[1])
+    return Hist(c, tuple(xrange), tuple(yrange), w, e)
 
 
 def _check_theta(th, model):

@@ -183,8 +183,13 @@ int check_hist(hf_ctx* c, const hf_hist* h, bool two_d) {
   if (h->nx > (int64_t(1) << 40) || h->ny > (int64_t(1) << 40) ||
       h->nx * h->ny > (int64_t(1) << 50))
     return fail(c, HF_EINVAL, "histogram too large");
-  if (!(std::isfinite(h->xlo) && std::isfinite(h->xhi) && h->xhi > h->xlo))
+  if (h->x_edges) {
+    if (two_d) return fail(c, HF_EUNSUPPORTED, "x_edges is for 1D histograms");
+    if ((reinterpret_cast<uintptr_t>(h->x_edges) & 7u) != 0)
+      return fail(c, HF_EINVAL, "x_edges must be 8-byte aligned");
+  } else if (!(std::isfinite(h->xlo) && std::isfinite(h->xhi) && h->xhi > h->xlo)) {
     return fail(c, HF_EINVAL, "x range must be finite with xhi > xlo");
+  }
   if (two_d && !(std::isfinite(h->ylo) && std::isfinite(h->yhi) && h->yhi > h->ylo))
     return fail(c, HF_EINVAL, "y range must be finite with yhi > ylo");
   if (!aligned16(h->counts)) return fail(c, HF_EINVAL, "hist.counts must be 16-byte aligned");
@@ -207,8 +212,10 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   if (prec != HF_FP64 && prec != HF_FP32_BIN)
     return fail(c, HF_EINVAL, "precision %d unknown", prec);
   const bool avg = m->bin_average != 0;
-  if (avg && prec != HF_FP64)
-    return fail(c, HF_EUNSUPPORTED, "bin-average models are evaluated in HF_FP64 only");
+  const bool edges = h->x_edges != nullptr;
+  if ((avg || edges) && prec != HF_FP64)
+    return fail(c, HF_EUNSUPPORTED,
+                "bin-average models and bins of any widths are evaluated in HF_FP64 only");
   if (!theta) return fail(c, HF_EINVAL, "theta is NULL");
   if (!nll_out) return fail(c, HF_EINVAL, "nll_out is NULL");
   if (grad && !grad_out) return fail(c, HF_EINVAL, "grad_out is NULL");
@@ -220,6 +227,15 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   hf::LaunchFn fn = nullptr;
   if (two_d) {
     fn = hf::pick_2d(obj, grad, prec == HF_FP32_BIN);
+  } else if (edges && !avg) {
+    switch (m->n_gauss) {
+      case 0: fn = hf::pick_edges_ng0(bkg_code(m), obj, grad); break;
+      case 1: fn = hf::pick_edges_ng1(bkg_code(m), obj, grad); break;
+      case 2: fn = hf::pick_edges_ng2(bkg_code(m), obj, grad); break;
+      case 3: fn = hf::pick_edges_ng3(bkg_code(m), obj, grad); break;
+      case 4: fn = hf::pick_edges_ng4(bkg_code(m), obj, grad); break;
+      default: break;
+    }
   } else if (avg) {
     switch (m->n_gauss) {
       case 0: fn = hf::pick_avg_ng0(m->poly_degree, obj, grad); break;
@@ -262,6 +278,7 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   a.part_flags = c->part_flags;
   a.ticket = c->ticket;
   a.log_lut = c->log_lut;
+  a.x_edges = h->x_edges;
   auto it = c->occupancy.find(fn);
   if (it == c->occupancy.end()) {
     int occ = 0;
@@ -277,9 +294,9 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   // 2D work items are 16-bin pieces of one row (a row's tail is a short piece)
   const int64_t items_bins =
       two_d ? ((a.nx + hf::kChunk2D - 1) / hf::kChunk2D) * hf::kChunk2D * a.ny : a.nx;
-  const int grid = objective_grid(
-      c, items_bins, two_d ? hf::kChunk2D : (avg ? hf::kAvgChunk : hf::chunk_bins(m->n_gauss)),
-      per_cu);
+  const int chunk = two_d ? hf::kChunk2D
+                          : (avg ? hf::kAvgChunk : (edges ? 1 : hf::chunk_bins(m->n_gauss)));
+  const int grid = objective_grid(c, items_bins, chunk, per_cu);
   hipError_t e = fn(a, grid, stream, nullptr);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return HF_OK;
@@ -417,6 +434,7 @@ HF_EXPORT int hf_nll_fisher(hf_ctx* c, const hf_hist* h, const hf_model* m, int3
   const bool two_d = m->kind == HF_GAUSS2D;
   rc = check_hist(c, h, two_d);
   if (rc) return rc;
+  if (h->x_edges) return fail(c, HF_EUNSUPPORTED, "the Fisher matrix takes uniform bins only");
   if (obj < HF_NEYMAN || obj > HF_POISSON) return fail(c, HF_EINVAL, "objective %d unknown", obj);
   if (!theta) return fail(c, HF_EINVAL, "theta is NULL");
   if (!fisher_out) return fail(c, HF_EINVAL, "fisher_out is NULL");

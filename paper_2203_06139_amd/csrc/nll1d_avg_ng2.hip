@@ -1,8 +1,9 @@
-// nll1d_avg_ng2.hip -- bin-average objective kernels with 2 Gaussian(s); one
-// translation unit per Gaussian count so the instantiations compile in
-// parallel.
+// nll1d_avg_ng2.hip -- bin-average and explicit-edge objective kernels with
+// 2 Gaussian(s); one translation unit per Gaussian count so the
+// instantiations compile in parallel.
 #include "nll_avg.hpp"
 
 namespace hf {
 LaunchFn pick_avg_ng2(int degree, int obj, bool grad) { return pick_avg_ng<2>(degree, obj, grad); }
+LaunchFn pick_edges_ng2(int bkg, int obj, bool grad) { return pick_edges_ng<2>(bkg, obj, grad); }
 }  // namespace hf

@@ -1,8 +1,9 @@
-// nll1d_avg_ng4.hip -- bin-average objective kernels with 4 Gaussian(s); one
-// translation unit per Gaussian count so the instantiations compile in
-// parallel.
+// nll1d_avg_ng4.hip -- bin-average and explicit-edge objective kernels with
+// 4 Gaussian(s); one translation unit per Gaussian count so the
+// instantiations compile in parallel.
 #include "nll_avg.hpp"
 
 namespace hf {
 LaunchFn pick_avg_ng4(int degree, int obj, bool grad) { return pick_avg_ng<4>(degree, obj, grad); }
+LaunchFn pick_edges_ng4(int bkg, int obj, bool grad) { return pick_edges_ng<4>(bkg, obj, grad); }
 }  // namespace hf

@@ -1,7 +1,13 @@
-// nll_avg.hpp -- objective (+ gradient) kernels of the bin-average 1D model:
-// mu_i is the Gauss + polynomial model's integral over bin i divided by the
-// bin width, instead of its value at the bin centre (the "integral of the
-// function in the bin" form of a binned fit).
+// nll_avg.hpp -- objective (+ gradient) kernels of the bin-average 1D model
+// and of histograms with bins of any widths.
+//
+// Bin average: mu_i is the Gauss + polynomial model's integral over bin i
+// divided by the bin width, instead of its value at the bin centre (the
+// "integral of the function in the bin" form of a binned fit).  Bins of any
+// widths (a.x_edges: nx + 1 ascending edges): the bin-average kernel takes
+// its edges from the array, and k_nll_1d_edges evaluates the centre model
+// at each bin's midpoint (one exp per Gaussian and bin: the uniform grid's
+// recurrences do not apply).
 //
 // Per Gaussian, with edges a < b of the bin, z_x = (x - m)/s and
 // e_x = exp(-z_x^2/2):
@@ -48,7 +54,6 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
   for (int g = 0; g < NG; ++g) sg[g] = a.theta[3 * g + 2];
   const double invh = 1.0 / a.hx;
   const double d = 0.5 * a.hx * M.ta;
-  const double d2 = d * d;
   if constexpr (OBJ == OBJ_POISSON) __syncthreads();
   double acc[NV];
 #pragma unroll
@@ -64,10 +69,12 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
   for (int64_t c = tid; c < nch; c += stride) {
     const int64_t i0 = c * kAvgChunk;
     const int len = static_cast<int>(nb - i0 < kAvgChunk ? nb - i0 : kAvgChunk);
+    const double* __restrict__ E = a.x_edges;
     // left edge of the chunk's first bin
     double za[G1], Ea[G1], ea[G1];
+    double xa = E ? E[i0] : fma(static_cast<double>(i0), a.hx, a.x0);
     {
-      const double x = fma(static_cast<double>(i0), a.hx, a.x0);
+      const double x = xa;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         za[g] = (x - M.m[g]) * M.is[g];
@@ -77,7 +84,8 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
     }
     for (int k = 0; k < len; ++k) {
       const int64_t i = i0 + k;
-      const double xb = fma(static_cast<double>(i + 1), a.hx, a.x0);
+      const double xb = E ? E[i + 1] : fma(static_cast<double>(i + 1), a.hx, a.x0);
+      const double ih = E ? 1.0 / (xb - xa) : invh;
       double mu = 0.0;
       double J[P];
 #pragma unroll
@@ -85,21 +93,23 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
         const double zb = (xb - M.m[g]) * M.is[g];
         const double Eb = erf(zb * kIr2);
         const double eb = exp_fast(-0.5 * zb * zb);
-        const double ia = sg[g] * kRt * (Eb - Ea[g]) * invh;
+        const double ia = sg[g] * kRt * (Eb - Ea[g]) * ih;
         const double mg = M.A[g] * ia;
         mu += mg;
         if constexpr (GRAD) {
           J[3 * g] = ia;
-          J[3 * g + 1] = M.A[g] * (ea[g] - eb) * invh;
-          J[3 * g + 2] = fma(mg, M.is[g], M.A[g] * fma(za[g], ea[g], -zb * eb) * invh);
+          J[3 * g + 1] = M.A[g] * (ea[g] - eb) * ih;
+          J[3 * g + 2] = fma(mg, M.is[g], M.A[g] * fma(za[g], ea[g], -zb * eb) * ih);
         }
         za[g] = zb;
         Ea[g] = Eb;
         ea[g] = eb;
       }
       if constexpr (S::NB > 0) {
-        const double xc = fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
+        const double xc = E ? 0.5 * (xa + xb) : fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
         const double tc = (xc - M.tshift) * M.ta;
+        const double dh = E ? 0.5 * (xb - xa) * M.ta : d;
+        const double d2 = dh * dh;
         double avg[4];
         avg[0] = 1.0;
         avg[1] = tc;
@@ -122,12 +132,137 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
         for (int p = 0; p < P; ++p) acc[1 + p] = fma(mb, J[p], acc[1 + p]);
       }
       if (a.grad_w_out) a.grad_w_out[i] = static_cast<float>(seed * l);
+      xa = xb;
     }
   }
   __shared__ double tot[NV];
   __shared__ int totf;
   if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
     write_outputs<NV>(a, UnitFactors{}, tot, totf, finite, gseed);
+}
+
+// Centre model on bins of any widths: mu at each bin's midpoint, with the
+// closed-form partials (A: e; m: G z; s: G z^2, the 1/s applied to the
+// totals; polynomial t^j; exponential E and t E), one exp per Gaussian.
+template <int NG, int BKG, int OBJ, bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_nll_1d_edges(NllArgs a) {
+  using S = Shape1D<NG, BKG>;
+  constexpr int P = S::P;
+  constexpr int NV = GRAD ? P + 1 : 1;
+  __shared__ double2 lut[OBJ == OBJ_POISSON ? kLogLut : 1];
+  if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
+  Model1D<NG, BKG> M;
+  M.init(a.theta, a.t_shift, a.t_scale);
+  if constexpr (OBJ == OBJ_POISSON) __syncthreads();
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  int flags = 0;
+  const double gseed = a.seed ? a.seed[0] : 1.0;
+  const double seed = a.grad_w_out ? gseed : 1.0;
+  const bool finite = all_finite(a.theta, a.P);
+  const double* __restrict__ E = a.x_edges;
+  const int64_t nb = a.nx;
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t i = tid; i < nb; i += stride) {
+    const double x = 0.5 * (E[i] + E[i + 1]);
+    double mu = 0.0;
+    double J[P];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const double z = (x - M.m[g]) * M.is[g];
+      const double e = exp_fast(-0.5 * z * z);
+      const double G = M.A[g] * e;
+      mu += G;
+      if constexpr (GRAD) {
+        const double Gz = G * z;
+        J[3 * g] = e;
+        J[3 * g + 1] = Gz;
+        J[3 * g + 2] = Gz * z;
+      }
+    }
+    const double t = (x - M.tshift) * M.ta;
+    if constexpr (BKG == BKG_EXP) {
+      const double Eb = exp_fast(fma(M.c[1], t, M.c[0]));
+      mu += Eb;
+      if constexpr (GRAD) {
+        J[3 * NG] = Eb;
+        J[3 * NG + 1] = t * Eb;
+      }
+    } else if constexpr (S::NB > 0) {
+      double b = M.c[S::NB - 1];
+#pragma unroll
+      for (int j = S::NB - 2; j >= 0; --j) b = fma(b, t, M.c[j]);
+      mu += b;
+      if constexpr (GRAD) {
+        double tj = 1.0;
+#pragma unroll
+        for (int j = 0; j < S::NB; ++j) {
+          J[3 * NG + j] = tj;
+          tj *= t;
+        }
+      }
+    }
+    const double n = load_count1(a, i);
+    const double w = a.weights ? static_cast<double>(a.weights[i]) : 1.0;
+    double l, ub;
+    flags |= objective_t<OBJ, false>(n, mu, lut, l, ub) ? ST_DOMAIN : 0;
+    acc[0] = fma(w, l, acc[0]);
+    if constexpr (GRAD) {
+      const double mb = w * ub;
+#pragma unroll
+      for (int p = 0; p < P; ++p) acc[1 + p] = fma(mb, J[p], acc[1 + p]);
+    }
+    if (a.grad_w_out) a.grad_w_out[i] = static_cast<float>(seed * l);
+  }
+  __shared__ double tot[NV];
+  __shared__ int totf;
+  if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
+    write_outputs<NV>(a, M, tot, totf, finite, gseed);
+}
+
+template <int NG, int BKG, int OBJ, bool GRAD>
+hipError_t launch_1d_edges(const NllArgs& a, int grid, hipStream_t s, int* occ) {
+  return launch_or_occupancy(k_nll_1d_edges<NG, BKG, OBJ, GRAD>, a, grid, s, occ);
+}
+
+template <int NG, int BKG>
+LaunchFn pick_edges_obj(int obj, bool grad) {
+  switch (obj) {
+    case OBJ_NEYMAN:
+      return grad ? &launch_1d_edges<NG, BKG, OBJ_NEYMAN, true>
+                  : &launch_1d_edges<NG, BKG, OBJ_NEYMAN, false>;
+    case OBJ_PEARSON:
+      return grad ? &launch_1d_edges<NG, BKG, OBJ_PEARSON, true>
+                  : &launch_1d_edges<NG, BKG, OBJ_PEARSON, false>;
+    case OBJ_POISSON:
+      return grad ? &launch_1d_edges<NG, BKG, OBJ_POISSON, true>
+                  : &launch_1d_edges<NG, BKG, OBJ_POISSON, false>;
+    default:
+      return nullptr;
+  }
+}
+
+template <int NG>
+LaunchFn pick_edges_ng(int bkg, int obj, bool grad) {
+  switch (bkg) {
+    case BKG_NONE:
+      if constexpr (NG == 0) return nullptr;
+      else return pick_edges_obj<NG, BKG_NONE>(obj, grad);
+    case 0:
+      return pick_edges_obj<NG, 0>(obj, grad);
+    case 1:
+      return pick_edges_obj<NG, 1>(obj, grad);
+    case 2:
+      return pick_edges_obj<NG, 2>(obj, grad);
+    case 3:
+      return pick_edges_obj<NG, 3>(obj, grad);
+    case BKG_EXP:
+      return pick_edges_obj<NG, BKG_EXP>(obj, grad);
+    default:
+      return nullptr;
+  }
 }
 
 template <int NG, int DEG, int OBJ, bool GRAD>
@@ -171,6 +306,11 @@ LaunchFn pick_avg_ng(int degree, int obj, bool grad) {
 }
 
 // Defined in nll1d_avg_ng{0..4}.hip.
+LaunchFn pick_edges_ng0(int bkg, int obj, bool grad);
+LaunchFn pick_edges_ng1(int bkg, int obj, bool grad);
+LaunchFn pick_edges_ng2(int bkg, int obj, bool grad);
+LaunchFn pick_edges_ng3(int bkg, int obj, bool grad);
+LaunchFn pick_edges_ng4(int bkg, int obj, bool grad);
 LaunchFn pick_avg_ng0(int degree, int obj, bool grad);
 LaunchFn pick_avg_ng1(int degree, int obj, bool grad);
 LaunchFn pick_avg_ng2(int degree, int obj, bool grad);

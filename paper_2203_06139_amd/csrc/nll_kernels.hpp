@@ -36,6 +36,7 @@ struct NllArgs {
   int32_t* part_flags;
   unsigned* ticket;
   const double2* log_lut;  // kLogLut entries, see log_lut_entry
+  const double* x_edges;   // 1D bins of any widths: nx + 1 ascending edges, or null
 };
 
 // Launches a kernel variant with `grid` blocks; grid <= 0 instead returns,
