@@ -77,7 +77,7 @@ typedef struct {
   int32_t kind;
   int32_t n_gauss;
   int32_t poly_degree;
-  int32_t bin_average; /* kind 1 only: 1 = mu_i is the bin average of the model */
+  int32_t bin_average; /* kinds 1, 2: 1 = mu_i is the bin average of the model */
   double t_shift;
   double t_scale;
 } or_model;
@@ -120,7 +120,7 @@ double or_neumaier_sum(const double* v, int64_t n) {
 /* ---------------------------------------------------------------------- */
 int or_nparams(const or_model* m) {
   if (!m) return -1;
-  if (m->bin_average && (m->kind != OR_GAUSS_POLY || m->poly_degree > 3)) return -1;
+  if (m->bin_average && (m->kind == OR_GAUSS2D || m->poly_degree > 3)) return -1;
   switch (m->kind) {
     case OR_GAUSS_POLY:
       if (m->n_gauss < 0 || m->poly_degree < -1) return -1;
@@ -206,6 +206,21 @@ static double centre(double lo, double hi, int64_t n, int64_t i) {
   return lo + ((double)i + 0.5) * h;
 }
 
+/* S(u) = sinh(u)/u and S'(u): the average of exp(b0 + b1 t) over
+ * [t_c - d, t_c + d] is exp(b0 + b1 t_c) S(b1 d).  For |u| < 1/2 the Taylor
+ * series to u^10 (truncation below 4e-14 relative); beyond, the closed
+ * forms, where cosh u - S(u) no longer cancels badly.                     */
+static void sinhc(double u, double* S, double* dS) {
+  if (fabs(u) < 0.5) {
+    double u2 = u * u;
+    *S = 1.0 + u2 / 6.0 * (1.0 + u2 / 20.0 * (1.0 + u2 / 42.0 * (1.0 + u2 / 72.0 * (1.0 + u2 / 110.0))));
+    *dS = u / 3.0 * (1.0 + u2 / 10.0 * (1.0 + u2 / 28.0 * (1.0 + u2 / 54.0 * (1.0 + u2 / 88.0))));
+  } else {
+    *S = sinh(u) / u;
+    *dS = (cosh(u) - *S) / u;
+  }
+}
+
 /* Bin average of the kind-1 model over [a, b] (h = b - a): the integral of
  * the model over the bin divided by the bin width, instead of its value at
  * the centre.  Per Gaussian, with z_x = (x - m)/s and e_x = exp(-z_x^2/2):
@@ -216,7 +231,9 @@ static double centre(double lo, double hi, int64_t n, int64_t i) {
  * Polynomial: the average of t^j over [t_c - d, t_c + d], t_c the bin
  * centre's t and d = h / (2 t_scale), is exactly
  *   1,  t_c,  t_c^2 + d^2/3,  t_c^3 + t_c d^2      (j = 0..3),
- * which is also dmu/dc_j.                                                  */
+ * which is also dmu/dc_j.  Exponential (kind 2): E_c S(b1 d) with
+ * E_c = exp(b0 + b1 t_c), S(u) = sinh(u)/u; d/db0 = itself,
+ * d/db1 = E_c (t_c S + d S').                                              */
 static double model1d_avg(const or_model* m, const double* th, double a, double b, double* dmu) {
   const double h = b - a;
   const double rt = sqrt(0.5 * 3.14159265358979323846), r2 = sqrt(2.0);
@@ -237,6 +254,18 @@ static double model1d_avg(const or_model* m, const double* th, double a, double 
   }
   double tc = (0.5 * (a + b) - m->t_shift) / m->t_scale;
   double d = 0.5 * h / m->t_scale;
+  if (m->kind == OR_GAUSS_EXP) {
+    /* average of exp(b0 + b1 t): E_c S(b1 d), E_c = exp(b0 + b1 t_c);
+     * d/db0 = itself, d/db1 = E_c (t_c S + d S')                          */
+    double Ec = exp(th[k] + th[k + 1] * tc), S, dS;
+    sinhc(th[k + 1] * d, &S, &dS);
+    mu += Ec * S;
+    if (dmu) {
+      dmu[k] = Ec * S;
+      dmu[k + 1] = Ec * (tc * S + d * dS);
+    }
+    return mu;
+  }
   double avg[4] = {1.0, tc, tc * tc + d * d / 3.0, tc * tc * tc + tc * d * d};
   for (int j = 0; j <= m->poly_degree; ++j) {
     mu += th[k + j] * avg[j];
@@ -507,13 +536,15 @@ int or_nll_grad(const or_model* m, int obj, const double* counts, const double* 
  * skipped; lambda <= 0 at an event inside is a domain error (L = +inf,
  * status bit 0).  Sums are Neumaier-compensated in event order; scale_out
  * (P+1 values, or NULL) receives |Lambda| + sum|w ln lambda| and, per
- * parameter, |dLambda/dtheta_k| + sum|w dlambda_k / lambda|.  Kind 1 only.
+ * parameter, |dLambda/dtheta_k| + sum|w dlambda_k / lambda|.  Kinds 1 and 2
+ * (the exponential's integral is (hi - lo) E_c S(b1 d) with E_c at the
+ * range's midpoint t_c and d its half-width in t; see sinhc).
  * Returns 0, -1 on bad arguments, -2 for an unsupported model.           */
 int or_unbinned(const or_model* m, const double* x, const double* weights, int64_t n, double lo,
                 double hi, const double* theta, double* nll_out, double* grad_out,
                 double* scale_out, int32_t* status_out) {
   int P = or_nparams(m);
-  if (P < 0 || P > OR_MAXP || m->kind != OR_GAUSS_POLY) return -2;
+  if (P < 0 || P > OR_MAXP || m->kind == OR_GAUSS2D) return -2;
   if ((n > 0 && !x) || !theta || !nll_out || !(hi > lo)) return -1;
   int32_t status = theta_finite(theta, P) ? 0 : OR_ST_NONFINITE;
   /* Lambda and its gradient */
@@ -532,7 +563,16 @@ int or_unbinned(const or_model* m, const double* x, const double* weights, int64
     dlam[k + 2] = lg / s + A * (zl * el - zh * eh);
   }
   double tl = (lo - m->t_shift) / m->t_scale, th = (hi - m->t_shift) / m->t_scale;
-  for (int j = 0; j <= m->poly_degree; ++j) {
+  if (m->kind == OR_GAUSS_EXP) {
+    /* integral of exp(b0 + b1 t) over the range: (hi - lo) E_c S(b1 d) */
+    double tc = 0.5 * (tl + th), d = 0.5 * (th - tl), S, dS;
+    double Ec = exp(theta[k] + theta[k + 1] * tc);
+    sinhc(theta[k + 1] * d, &S, &dS);
+    lam_tot += (hi - lo) * Ec * S;
+    dlam[k] = (hi - lo) * Ec * S;
+    dlam[k + 1] = (hi - lo) * Ec * (tc * S + d * dS);
+  }
+  for (int j = 0; m->kind == OR_GAUSS_POLY && j <= m->poly_degree; ++j) {
     double ij = m->t_scale * (pow(th, j + 1) - pow(tl, j + 1)) / (j + 1);
     lam_tot += theta[k + j] * ij;
     dlam[k + j] = ij;

@@ -168,3 +168,109 @@ def test_uniform_edges_reproduce_the_range_form(orc):
         b = orc.nll_grad(M, 1, n, th, r)
         assert abs(a.nll - b.nll) <= 1e-13 * b.scales[0]
         assert np.all(np.abs(a.grad - b.grad) <= 1e-13 * b.scales[1:])
+
+
+# ---------------------------------------------------------------------------
+# Exponential background: bin average and unbinned integral
+# ---------------------------------------------------------------------------
+EXP_CASES = [
+    (1, [300.0, 4.0, 0.8, math.log(20.0), 0.6]),
+    (0, [math.log(50.0), -2.5]),
+    (1, [200.0, 6.0, 0.5, math.log(5.0), 0.0]),    # b1 = 0: S(0) = 1, S'(0) = 0
+    (2, [100.0, 2.0, 0.4, 80.0, 7.0, 1.0, math.log(3.0), 4.0]),
+]
+
+
+def np_exp_f(th, x, ng):
+    lam = 0.0 * x
+    for g in range(ng):
+        A, m, s = th[3 * g: 3 * g + 3]
+        lam = lam + A * np.exp(-((x - m) / s) ** 2 / 2)
+    return lam + np.exp(th[3 * ng] + th[3 * ng + 1] * (x - T_SHIFT) / T_SCALE)
+
+
+def np_exp_avg(th, a, b, ng):
+    h = b - a
+    mu = 0.0 * a
+    for g in range(ng):
+        A, m, s = th[3 * g: 3 * g + 3]
+        mu = mu + A * s * math.sqrt(math.pi / 2) * (special.erf((b - m) / (s * math.sqrt(2))) -
+                                                     special.erf((a - m) / (s * math.sqrt(2)))) / h
+    # the average of exp(b0 + b1 t) over [t_c - d, t_c + d] written as
+    # exp(b0 + b1 t_c) sinh(u)/u, u = b1 d: exact, and unlike the difference
+    # of antiderivatives free of cancellation for small b1 d (the complex
+    # step then differentiates it to full accuracy)
+    b0, b1 = th[3 * ng], th[3 * ng + 1]
+    ta, tb = (a - T_SHIFT) / T_SCALE, (b - T_SHIFT) / T_SCALE
+    tc, d = 0.5 * (ta + tb), 0.5 * (tb - ta)
+    u = b1 * d
+    return mu + np.exp(b0 + b1 * tc) * np.sinh(u) / u
+
+
+@pytest.mark.parametrize("case", range(len(EXP_CASES)))
+def test_exp_bin_average_by_quadrature(orc, case):
+    ng, th = EXP_CASES[case]
+    e = _edges(0.0, 10.0, 30, seed=40 + case)
+    M = orc.Model(2, ng, -1, T_SHIFT, T_SCALE, bin_average=1)
+    mu = _mu_from_ell(orc, M, e, th)
+    for i in range(e.size - 1):
+        q, _ = integrate.quad(lambda x: float(np_exp_f(np.array(th), np.array([x]), ng)[0]),
+                              e[i], e[i + 1], epsabs=0, epsrel=1e-13, limit=200)
+        assert mu[i] == pytest.approx(q / (e[i + 1] - e[i]), rel=1e-11), i
+
+
+@pytest.mark.parametrize("case", range(len(EXP_CASES)))
+def test_exp_bin_average_gradient_by_complex_step(orc, case):
+    ng, th = EXP_CASES[case]
+    if th[-1] == 0.0:
+        th = th[:-1] + [1e-3]  # the complex step needs b1 != 0 in the antiderivative form
+    e = _edges(0.0, 10.0, 40, seed=50 + case)
+    M = orc.Model(2, ng, -1, T_SHIFT, T_SCALE, bin_average=1)
+    n = np.random.default_rng(case).poisson(np.maximum(_mu_from_ell(orc, M, e, th), 0.5))
+    ref = orc.nll_grad_edges(M, 2, n.astype(np.float64), e, th)
+
+    def L(tc):
+        m = np_exp_avg(tc, e[:-1] + 0j, e[1:] + 0j, ng)
+        return np.sum(m - n + np.where(n > 0, n * np.log(np.where(n > 0, n, 1) / m), 0))
+
+    for k in range(len(th)):
+        tc = np.array(th, dtype=complex)
+        tc[k] += 1j * 1e-30
+        cs = np.imag(L(tc)) / 1e-30
+        assert abs(ref.grad[k] - cs) <= 1e-10 * ref.scales[1 + k], (k, ref.grad[k], cs)
+
+
+@pytest.mark.parametrize("case", range(len(EXP_CASES)))
+def test_exp_unbinned_integral_and_gradient(orc, case):
+    """Lambda for the exponential background over the whole range, where
+    b1 (t_hi - t_lo)/2 reaches the closed-form branch, against quadrature;
+    the gradient against the complex step."""
+    ng, th = EXP_CASES[case]
+    M = orc.Model(2, ng, -1, T_SHIFT, T_SCALE)
+    lo, hi = 0.0, 10.0
+    r0 = orc.unbinned(M, np.array([]), lo, hi, th)
+    q, _ = integrate.quad(lambda x: float(np_exp_f(np.array(th), np.array([x]), ng)[0]), lo, hi,
+                          epsabs=0, epsrel=1e-13, limit=200)
+    assert r0.nll == pytest.approx(q, rel=1e-12)
+    if th[-1] == 0.0:
+        th = th[:-1] + [1e-3]
+    x = np.random.default_rng(case).uniform(lo, hi, 300)
+    r = orc.unbinned(M, x, lo, hi, th)
+
+    def L(tc):
+        Lam = 0.0
+        for g in range(ng):
+            A, m, s = tc[3 * g: 3 * g + 3]
+            Lam = Lam + A * s * math.sqrt(math.pi / 2) * (
+                special.erf((hi - m) / (s * math.sqrt(2))) - special.erf((lo - m) / (s * math.sqrt(2))))
+        b0, b1 = tc[3 * ng], tc[3 * ng + 1]
+        tl, th_ = (lo - T_SHIFT) / T_SCALE, (hi - T_SHIFT) / T_SCALE
+        u = b1 * 0.5 * (th_ - tl)
+        Lam = Lam + (hi - lo) * np.exp(b0 + b1 * 0.5 * (tl + th_)) * np.sinh(u) / u
+        return Lam - np.sum(np.log(np_exp_f(tc, x + 0j, ng)))
+
+    for k in range(len(th)):
+        tc = np.array(th, dtype=complex)
+        tc[k] += 1j * 1e-30
+        cs = np.imag(L(tc)) / 1e-30
+        assert abs(r.grad[k] - cs) <= 1e-11 * r.scales[1 + k], (k, r.grad[k], cs)
