@@ -96,8 +96,8 @@ int check_model(hf_ctx* c, const hf_model* m, bool allow_avg = false) {
   if (!m) return fail(c, HF_EINVAL, "model is NULL");
   if (m->bin_average != 0 && m->bin_average != 1)
     return fail(c, HF_EINVAL, "model.bin_average must be 0 or 1");
-  if (m->bin_average && m->kind != HF_GAUSS_POLY)
-    return fail(c, HF_EUNSUPPORTED, "bin-average models are HF_GAUSS_POLY only");
+  if (m->bin_average && m->kind == HF_GAUSS2D)
+    return fail(c, HF_EUNSUPPORTED, "bin-average models are 1D only");
   if (m->bin_average && !allow_avg)
     return fail(c, HF_EUNSUPPORTED, "this call does not take bin-average models");
   switch (m->kind) {
@@ -238,11 +238,11 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
     }
   } else if (avg) {
     switch (m->n_gauss) {
-      case 0: fn = hf::pick_avg_ng0(m->poly_degree, obj, grad); break;
-      case 1: fn = hf::pick_avg_ng1(m->poly_degree, obj, grad); break;
-      case 2: fn = hf::pick_avg_ng2(m->poly_degree, obj, grad); break;
-      case 3: fn = hf::pick_avg_ng3(m->poly_degree, obj, grad); break;
-      case 4: fn = hf::pick_avg_ng4(m->poly_degree, obj, grad); break;
+      case 0: fn = hf::pick_avg_ng0(bkg_code(m), obj, grad); break;
+      case 1: fn = hf::pick_avg_ng1(bkg_code(m), obj, grad); break;
+      case 2: fn = hf::pick_avg_ng2(bkg_code(m), obj, grad); break;
+      case 3: fn = hf::pick_avg_ng3(bkg_code(m), obj, grad); break;
+      case 4: fn = hf::pick_avg_ng4(bkg_code(m), obj, grad); break;
       default: break;
     }
   } else {
@@ -382,8 +382,8 @@ HF_EXPORT int nll_unbinned(hf_ctx* c, const double* events, const float* weights
   if (!c) return HF_EINVAL;
   int rc = check_model(c, m);
   if (rc) return rc;
-  if (m->kind != HF_GAUSS_POLY)
-    return fail(c, HF_EUNSUPPORTED, "the unbinned NLL supports HF_GAUSS_POLY models only");
+  if (m->kind == HF_GAUSS2D)
+    return fail(c, HF_EUNSUPPORTED, "the unbinned NLL takes 1D models");
   if (n_events < 0) return fail(c, HF_EINVAL, "n_events must be >= 0");
   if (n_events > 0 && !events) return fail(c, HF_EINVAL, "events is NULL");
   if (!(std::isfinite(lo) && std::isfinite(hi) && hi > lo))
@@ -394,11 +394,11 @@ HF_EXPORT int nll_unbinned(hf_ctx* c, const double* events, const float* weights
   if (rc) return rc;
   hf::UnbinnedFn fn = nullptr;
   switch (m->n_gauss) {
-    case 0: fn = hf::pick_unbinned_ng0(m->poly_degree); break;
-    case 1: fn = hf::pick_unbinned_ng1(m->poly_degree); break;
-    case 2: fn = hf::pick_unbinned_ng2(m->poly_degree); break;
-    case 3: fn = hf::pick_unbinned_ng3(m->poly_degree); break;
-    case 4: fn = hf::pick_unbinned_ng4(m->poly_degree); break;
+    case 0: fn = hf::pick_unbinned_ng0(bkg_code(m)); break;
+    case 1: fn = hf::pick_unbinned_ng1(bkg_code(m)); break;
+    case 2: fn = hf::pick_unbinned_ng2(bkg_code(m)); break;
+    case 3: fn = hf::pick_unbinned_ng3(bkg_code(m)); break;
+    case 4: fn = hf::pick_unbinned_ng4(bkg_code(m)); break;
     default: break;
   }
   if (!fn) return fail(c, HF_EUNSUPPORTED, "no unbinned kernel for this model");

@@ -123,4 +123,19 @@ __device__ __forceinline__ double log_lut(double x, const double2* __restrict__ 
   return fma(p, f, fma(ed, kLn2, t.y));
 }
 
+// S(u) = sinh(u)/u and S'(u) = (cosh u - S(u))/u: the average of
+// exp(b0 + b1 t) over [t_c - d, t_c + d] is exp(b0 + b1 t_c) S(b1 d).  Taylor
+// series to u^10 for |u| < 1/2 (truncation below 4e-14 relative), the
+// closed forms beyond, where cosh u - S(u) no longer cancels badly.
+__device__ __forceinline__ void sinhc(double u, double& S, double& dS) {
+  if (fabs(u) < 0.5) {
+    const double u2 = u * u;
+    S = 1.0 + u2 / 6.0 * (1.0 + u2 / 20.0 * (1.0 + u2 / 42.0 * (1.0 + u2 / 72.0 * (1.0 + u2 / 110.0))));
+    dS = u / 3.0 * (1.0 + u2 / 10.0 * (1.0 + u2 / 28.0 * (1.0 + u2 / 54.0 * (1.0 + u2 / 88.0))));
+  } else {
+    S = sinh(u) / u;
+    dS = (cosh(u) - S) / u;
+  }
+}
+
 }  // namespace hf

@@ -16,7 +16,9 @@
 //   dmu/dm = A (e_a - e_b) / h
 //   dmu/ds = mu_g / s + A (z_a e_a - z_b e_b) / h
 // and for the polynomial in t the exact bin averages of t^j
-//   1, t_c, t_c^2 + d^2/3, t_c^3 + t_c d^2   (d = h / (2 t_scale)).
+//   1, t_c, t_c^2 + d^2/3, t_c^3 + t_c d^2   (d = h / (2 t_scale)),
+// for the exponential exp(b0 + b1 t) its exact average E_c S(b1 d) with
+// E_c = exp(b0 + b1 t_c) and S(u) = sinh(u)/u (d/db1 = E_c (t_c S + d S')).
 // A thread walks a chunk of consecutive bins edge to edge: each bin
 // evaluates erf and exp at its right edge and hands them to the next bin, so
 // a bin costs one erf and one exp per Gaussian.  The objective terms, the
@@ -37,9 +39,9 @@ struct UnitFactors {
 };
 
 // a.x0 holds the left edge of bin 0 (not its centre) for these kernels.
-template <int NG, int DEG, int OBJ, bool GRAD>
+template <int NG, int BKG, int OBJ, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
-  using S = Shape1D<NG, DEG>;
+  using S = Shape1D<NG, BKG>;
   constexpr int P = S::P;
   constexpr int NV = GRAD ? P + 1 : 1;
   constexpr int G1 = NG > 0 ? NG : 1;
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
   constexpr double kIr2 = 0.70710678118654752440;  // 1/sqrt(2)
   __shared__ double2 lut[OBJ == OBJ_POISSON ? kLogLut : 1];
   if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
-  Model1D<NG, DEG> M;
+  Model1D<NG, BKG> M;
   M.init(a.theta, a.t_shift, a.t_scale);
   double sg[G1];
 #pragma unroll
@@ -105,7 +107,20 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
         Ea[g] = Eb;
         ea[g] = eb;
       }
-      if constexpr (S::NB > 0) {
+      if constexpr (BKG == BKG_EXP) {
+        const double xc = E ? 0.5 * (xa + xb) : fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
+        const double tc = (xc - M.tshift) * M.ta;
+        const double dh = E ? 0.5 * (xb - xa) * M.ta : d;
+        const double Ec = exp_fast(fma(M.c[1], tc, M.c[0]));
+        double Sh, dSh;
+        sinhc(M.c[1] * dh, Sh, dSh);
+        const double eb = Ec * Sh;
+        mu += eb;
+        if constexpr (GRAD) {
+          J[3 * NG] = eb;
+          J[3 * NG + 1] = Ec * fma(tc, Sh, dh * dSh);
+        }
+      } else if constexpr (S::NB > 0) {
         const double xc = E ? 0.5 * (xa + xb) : fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
         const double tc = (xc - M.tshift) * M.ta;
         const double dh = E ? 0.5 * (xb - xa) * M.ta : d;
@@ -265,30 +280,31 @@ LaunchFn pick_edges_ng(int bkg, int obj, bool grad) {
   }
 }
 
-template <int NG, int DEG, int OBJ, bool GRAD>
+template <int NG, int BKG, int OBJ, bool GRAD>
 hipError_t launch_1d_avg(const NllArgs& a, int grid, hipStream_t s, int* occ) {
-  return launch_or_occupancy(k_nll_1d_avg<NG, DEG, OBJ, GRAD>, a, grid, s, occ);
+  return launch_or_occupancy(k_nll_1d_avg<NG, BKG, OBJ, GRAD>, a, grid, s, occ);
 }
 
-template <int NG, int DEG>
+template <int NG, int BKG>
 LaunchFn pick_avg_obj(int obj, bool grad) {
   switch (obj) {
     case OBJ_NEYMAN:
-      return grad ? &launch_1d_avg<NG, DEG, OBJ_NEYMAN, true> : &launch_1d_avg<NG, DEG, OBJ_NEYMAN, false>;
+      return grad ? &launch_1d_avg<NG, BKG, OBJ_NEYMAN, true> : &launch_1d_avg<NG, BKG, OBJ_NEYMAN, false>;
     case OBJ_PEARSON:
-      return grad ? &launch_1d_avg<NG, DEG, OBJ_PEARSON, true>
-                  : &launch_1d_avg<NG, DEG, OBJ_PEARSON, false>;
+      return grad ? &launch_1d_avg<NG, BKG, OBJ_PEARSON, true>
+                  : &launch_1d_avg<NG, BKG, OBJ_PEARSON, false>;
     case OBJ_POISSON:
-      return grad ? &launch_1d_avg<NG, DEG, OBJ_POISSON, true>
-                  : &launch_1d_avg<NG, DEG, OBJ_POISSON, false>;
+      return grad ? &launch_1d_avg<NG, BKG, OBJ_POISSON, true>
+                  : &launch_1d_avg<NG, BKG, OBJ_POISSON, false>;
     default:
       return nullptr;
   }
 }
 
+// bkg: the background code (polynomial degree -1..3, or BKG_EXP).
 template <int NG>
-LaunchFn pick_avg_ng(int degree, int obj, bool grad) {
-  switch (degree) {
+LaunchFn pick_avg_ng(int bkg, int obj, bool grad) {
+  switch (bkg) {
     case -1:
       if constexpr (NG == 0) return nullptr;
       else return pick_avg_obj<NG, BKG_NONE>(obj, grad);
@@ -300,6 +316,8 @@ LaunchFn pick_avg_ng(int degree, int obj, bool grad) {
       return pick_avg_obj<NG, 2>(obj, grad);
     case 3:
       return pick_avg_obj<NG, 3>(obj, grad);
+    case BKG_EXP:
+      return pick_avg_obj<NG, BKG_EXP>(obj, grad);
     default:
       return nullptr;
   }
@@ -311,10 +329,10 @@ LaunchFn pick_edges_ng1(int bkg, int obj, bool grad);
 LaunchFn pick_edges_ng2(int bkg, int obj, bool grad);
 LaunchFn pick_edges_ng3(int bkg, int obj, bool grad);
 LaunchFn pick_edges_ng4(int bkg, int obj, bool grad);
-LaunchFn pick_avg_ng0(int degree, int obj, bool grad);
-LaunchFn pick_avg_ng1(int degree, int obj, bool grad);
-LaunchFn pick_avg_ng2(int degree, int obj, bool grad);
-LaunchFn pick_avg_ng3(int degree, int obj, bool grad);
-LaunchFn pick_avg_ng4(int degree, int obj, bool grad);
+LaunchFn pick_avg_ng0(int bkg, int obj, bool grad);
+LaunchFn pick_avg_ng1(int bkg, int obj, bool grad);
+LaunchFn pick_avg_ng2(int bkg, int obj, bool grad);
+LaunchFn pick_avg_ng3(int bkg, int obj, bool grad);
+LaunchFn pick_avg_ng4(int bkg, int obj, bool grad);
 
 }  // namespace hf

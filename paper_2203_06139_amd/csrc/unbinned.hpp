@@ -3,7 +3,7 @@
 // positions (the per-event batch evaluation of RooFit-style likelihoods).
 //
 // For events x_e with weights w_e (default 1) and the 1D Gauss + polynomial
-// model read as an intensity lambda(x; theta):
+// or exponential model read as an intensity lambda(x; theta):
 //   L(theta) = Lambda(theta) - sum_e w_e ln lambda(x_e),
 //   Lambda   = integral of lambda over [lo, hi]   (the expected count),
 // the extended likelihood of a Poisson process (the binned Poisson objective
@@ -17,6 +17,7 @@
 //   d/dA = Lambda_g/A,  d/dm = A (e_lo - e_hi),
 //   d/ds = Lambda_g/s + A (z_lo e_lo - z_hi e_hi);
 //   polynomial: d/dc_j = t_scale (t_hi^(j+1) - t_lo^(j+1))/(j+1);
+//   exponential: (hi - lo) E_c S(b1 d), E_c = exp(b0 + b1 t_c), S = sinh(u)/u;
 // thread 0 of every block computes them into LDS during the prologue, and
 // the block that finishes the grid reduction adds them.  Events outside
 // [lo, hi] are skipped; lambda <= 0 at an event inside is a domain error.
@@ -74,7 +75,15 @@ __device__ __forceinline__ void event_term(const UnbinnedArgs& a, const Model1D<
       J[3 * g + 2] = Gz * z;
     }
   }
-  if constexpr (S::NB > 0) {
+  if constexpr (BKG == BKG_EXP) {
+    const double t = (x - M.tshift) * M.ta;
+    const double Eb = exp_fast(fma(M.c[1], t, M.c[0]));
+    lam += Eb;
+    if constexpr (GRAD) {
+      J[3 * NG] = Eb;
+      J[3 * NG + 1] = t * Eb;
+    }
+  } else if constexpr (S::NB > 0) {
     const double t = (x - M.tshift) * M.ta;
     double b = M.c[S::NB - 1];
 #pragma unroll
@@ -120,7 +129,18 @@ __device__ void lambda_terms(const UnbinnedArgs& a, const Model1D<NG, BKG>& M, d
     out[2 + 3 * g] = M.A[g] * (el - eh);
     out[3 + 3 * g] = lg * M.is[g] + M.A[g] * (zl * el - zh * eh);
   }
-  if constexpr (S::NB > 0) {
+  if constexpr (BKG == BKG_EXP) {
+    // (hi - lo) E_c S(b1 d) over the range, E_c at its midpoint t_c, d its
+    // half-width in t (S = sinh(u)/u, see sinhc)
+    const double tl = (a.lo - M.tshift) * M.ta, th = (a.hi - M.tshift) * M.ta;
+    const double tc = 0.5 * (tl + th), d = 0.5 * (th - tl), w = a.hi - a.lo;
+    const double Ec = exp(fma(M.c[1], tc, M.c[0]));
+    double Sh, dSh;
+    sinhc(M.c[1] * d, Sh, dSh);
+    lam = fma(w * Ec, Sh, lam);
+    out[1 + 3 * NG] = w * Ec * Sh;
+    out[2 + 3 * NG] = w * Ec * fma(tc, Sh, d * dSh);
+  } else if constexpr (S::NB > 0) {
     const double tl = (a.lo - M.tshift) * M.ta, th = (a.hi - M.tshift) * M.ta;
     double pl = tl, ph = th;
 #pragma unroll
@@ -230,9 +250,10 @@ hipError_t launch_unbinned(const UnbinnedArgs& a, bool vec, int num_cu, int max_
              : launch_unbinned_v<NG, BKG, false, false>(a, num_cu, max_grid, s);
 }
 
+// bkg: the background code (polynomial degree -1..3, or BKG_EXP).
 template <int NG>
-UnbinnedFn pick_unbinned_ng(int degree) {
-  switch (degree) {
+UnbinnedFn pick_unbinned_ng(int bkg) {
+  switch (bkg) {
     case -1:
       if constexpr (NG == 0) return nullptr;
       else return &launch_unbinned<NG, BKG_NONE>;
@@ -244,16 +265,18 @@ UnbinnedFn pick_unbinned_ng(int degree) {
       return &launch_unbinned<NG, 2>;
     case 3:
       return &launch_unbinned<NG, 3>;
+    case BKG_EXP:
+      return &launch_unbinned<NG, BKG_EXP>;
     default:
       return nullptr;
   }
 }
 
 // Defined in unbinned_ng{0..4}.hip.
-UnbinnedFn pick_unbinned_ng0(int degree);
-UnbinnedFn pick_unbinned_ng1(int degree);
-UnbinnedFn pick_unbinned_ng2(int degree);
-UnbinnedFn pick_unbinned_ng3(int degree);
-UnbinnedFn pick_unbinned_ng4(int degree);
+UnbinnedFn pick_unbinned_ng0(int bkg);
+UnbinnedFn pick_unbinned_ng1(int bkg);
+UnbinnedFn pick_unbinned_ng2(int bkg);
+UnbinnedFn pick_unbinned_ng3(int bkg);
+UnbinnedFn pick_unbinned_ng4(int bkg);
 
 }  // namespace hf

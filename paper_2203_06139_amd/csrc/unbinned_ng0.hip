@@ -4,5 +4,5 @@
 #include "unbinned.hpp"
 
 namespace hf {
-UnbinnedFn pick_unbinned_ng0(int degree) { return pick_unbinned_ng<0>(degree); }
+UnbinnedFn pick_unbinned_ng0(int bkg) { return pick_unbinned_ng<0>(bkg); }
 }  // namespace hf

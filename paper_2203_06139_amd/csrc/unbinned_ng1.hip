@@ -4,5 +4,5 @@
 #include "unbinned.hpp"
 
 namespace hf {
-UnbinnedFn pick_unbinned_ng1(int degree) { return pick_unbinned_ng<1>(degree); }
+UnbinnedFn pick_unbinned_ng1(int bkg) { return pick_unbinned_ng<1>(bkg); }
 }  // namespace hf

@@ -4,5 +4,5 @@
 #include "unbinned.hpp"
 
 namespace hf {
-UnbinnedFn pick_unbinned_ng2(int degree) { return pick_unbinned_ng<2>(degree); }
+UnbinnedFn pick_unbinned_ng2(int bkg) { return pick_unbinned_ng<2>(bkg); }
 }  // namespace hf

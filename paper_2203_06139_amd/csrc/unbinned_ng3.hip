@@ -4,5 +4,5 @@
 #include "unbinned.hpp"
 
 namespace hf {
-UnbinnedFn pick_unbinned_ng3(int degree) { return pick_unbinned_ng<3>(degree); }
+UnbinnedFn pick_unbinned_ng3(int bkg) { return pick_unbinned_ng<3>(bkg); }
 }  // namespace hf

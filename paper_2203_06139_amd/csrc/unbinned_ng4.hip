@@ -4,5 +4,5 @@
 #include "unbinned.hpp"
 
 namespace hf {
-UnbinnedFn pick_unbinned_ng4(int degree) { return pick_unbinned_ng<4>(degree); }
+UnbinnedFn pick_unbinned_ng4(int bkg) { return pick_unbinned_ng<4>(bkg); }
 }  // namespace hf

@@ -89,6 +89,8 @@ def test_bin_average_flag_is_validated_on_the_host(lib):
     import paper_2203_06139_amd as hf
     assert hf.Model(hf.GAUSS_POLY, 2, 3, 50, 50, bin_average=1).nparams == 10
     m = hf.HfModel(hf.GAUSS_EXP, 1, -1, 1, 0.0, 1.0)  # bin average of the exponential model
+    assert lib.hf_model_nparams(ctypes.byref(m)) == 5
+    m = hf.HfModel(hf.GAUSS2D, 0, -1, 1, 0.0, 1.0)  # no bin average in 2D
     assert lib.hf_model_nparams(ctypes.byref(m)) == -2
     m = hf.HfModel(hf.GAUSS_POLY, 1, 1, 2, 0.0, 1.0)  # flag must be 0 or 1
     assert lib.hf_model_nparams(ctypes.byref(m)) == -1

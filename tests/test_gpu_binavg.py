@@ -23,6 +23,10 @@ CASES = [
      (0.0, 10.0)),
     (datagen.model_spec(1, 0, 2, 0.5, 2.0), [50.0, 10.0, -8.0], (-2.0, 2.0)),
     (datagen.model_spec(1, 1, -1, 0.0, 1.0), [400.0, 5.0, 1.5], (0.0, 10.0)),
+    (datagen.model_spec(2, 1, -1, 0.0, 1.0), [500.0, 0.45, 0.05, math.log(200.0), math.log(0.3)],
+     (0.0, 1.0)),
+    (datagen.model_spec(2, 2, -1, 5.0, 5.0),
+     [300.0, 3.0, 0.4, 200.0, 7.0, 0.7, math.log(30.0), 0.0], (0.0, 10.0)),
 ]
 
 
@@ -79,6 +83,7 @@ def test_bin_average_differs_from_centre_by_curvature(hf, orc):
     """Sanity against the centre model: for wide bins the two objectives
     differ, and the oracle agrees about by how much."""
     spec, th, r = CASES[5]
+    assert spec["kind"] == 1 and spec["poly_degree"] == -1
     c = datagen.random_1d_case(spec, 40, r[0], r[1], th, seed=5)
     nll_avg, _, _, _, _ = gpu(hf, spec, c["counts"], th, r, 2)
     ref_avg = orc.nll_grad(orc_model(orc, spec), 2, c["counts"], th, r).nll
@@ -101,9 +106,10 @@ def test_bin_average_unsupported_calls(hf):
         hf.fit_batch(c, torch.tensor([0, 64], device="cuda"),
                      torch.tensor([[0.0, 10.0]], device="cuda", dtype=torch.float64), m,
                      torch.tensor([CASES[0][1]], device="cuda", dtype=torch.float64))
-    bad = hf.Model(hf.GAUSS_EXP, 1, -1, bin_average=1)
+    bad = hf.Model(hf.GAUSS2D, bin_average=1)
+    h2 = hf.make_hist(np.ones((8, 8), dtype=np.uint32), (0.0, 1.0), (0.0, 1.0))
     with pytest.raises((ValueError, hf.HistfitError)):
-        hf.nll_grad(h, bad, [1.0, 5.0, 1.0, 0.0, 0.0])
+        hf.nll_grad(h2, bad, [1.0, 0.5, 0.5, 0.1, 0.1, 0.0, 1.0])
 
 
 @pytest.mark.slow

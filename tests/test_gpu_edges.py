@@ -65,7 +65,7 @@ def check(ref, nll, grad, what):
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_edges_parity(hf, orc, case, obj):
     spec, th, r = CASES[case]
-    avgs = (0, 1) if spec["kind"] == 1 else (0,)
+    avgs = (0, 1)
     for avg in avgs:
         for nb, weighted in ((1, False), (3, True), (65, False), (4099, True), (100_003, False)):
             e = edges_for(r[0], r[1], nb, seed=nb + case)

@@ -26,6 +26,8 @@ CASES = [
     (datagen.model_spec(1, 3, 0, 0.0, 1.0), [80.0, 2.0, 0.5, 120.0, 5.0, 0.8, 60.0, 7.5, 0.4, 15.0]),
     (datagen.model_spec(1, 4, 3, 5.0, 5.0),
      [80.0, 2.0, 0.5, 120.0, 5.0, 0.8, 60.0, 7.5, 0.4, 50.0, 8.8, 0.3, 15.0, 1.0, -0.5, 0.2]),
+    (datagen.model_spec(2, 1, -1, 5.0, 5.0), [300.0, 4.0, 0.8, math.log(20.0), 1.2]),
+    (datagen.model_spec(2, 0, -1, 0.0, 5.0), [math.log(80.0), -1.5]),
 ]
 
 
@@ -95,9 +97,8 @@ def test_unbinned_misaligned_and_status(hf, orc):
     assert st & 2 and math.isnan(nll) and np.all(np.isnan(grad))
     with pytest.raises(hf.HistfitError):
         hf.nll_unbinned(xa, 1.0, 1.0, hf.Model.from_spec(spec), th)
-    with pytest.raises(hf.HistfitError):
-        hf.nll_unbinned(xa, 0.0, 1.0, hf.Model.from_spec(datagen.model_spec(2, 1, -1)),
-                        [1.0, 0.5, 0.1, 0.0, 0.0])
+    with pytest.raises((ValueError, hf.HistfitError)):
+        hf.nll_unbinned(xa, 0.0, 1.0, hf.Model(hf.GAUSS2D), [1.0, 0.5, 0.5, 0.1, 0.1, 0.0, 1.0])
 
 
 def test_unbinned_deterministic(hf):
