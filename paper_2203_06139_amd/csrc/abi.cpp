@@ -238,11 +238,11 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
     }
   } else if (avg) {
     switch (m->n_gauss) {
-      case 0: fn = hf::pick_avg_ng0(bkg_code(m), obj, grad); break;
-      case 1: fn = hf::pick_avg_ng1(bkg_code(m), obj, grad); break;
-      case 2: fn = hf::pick_avg_ng2(bkg_code(m), obj, grad); break;
-      case 3: fn = hf::pick_avg_ng3(bkg_code(m), obj, grad); break;
-      case 4: fn = hf::pick_avg_ng4(bkg_code(m), obj, grad); break;
+      case 0: fn = hf::pick_avg_ng0(bkg_code(m), obj, grad, edges); break;
+      case 1: fn = hf::pick_avg_ng1(bkg_code(m), obj, grad, edges); break;
+      case 2: fn = hf::pick_avg_ng2(bkg_code(m), obj, grad, edges); break;
+      case 3: fn = hf::pick_avg_ng3(bkg_code(m), obj, grad, edges); break;
+      case 4: fn = hf::pick_avg_ng4(bkg_code(m), obj, grad, edges); break;
       default: break;
     }
   } else {

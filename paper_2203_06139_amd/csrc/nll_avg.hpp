@@ -39,7 +39,9 @@ struct UnitFactors {
 };
 
 // a.x0 holds the left edge of bin 0 (not its centre) for these kernels.
-template <int NG, int BKG, int OBJ, bool GRAD>
+// EDGES: the bins' edges come from a.x_edges (any widths), else from the
+// uniform grid.
+template <int NG, int BKG, int OBJ, bool GRAD, bool EDGES>
 __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
   using S = Shape1D<NG, BKG>;
   constexpr int P = S::P;
@@ -71,10 +73,10 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
   for (int64_t c = tid; c < nch; c += stride) {
     const int64_t i0 = c * kAvgChunk;
     const int len = static_cast<int>(nb - i0 < kAvgChunk ? nb - i0 : kAvgChunk);
-    const double* __restrict__ E = a.x_edges;
+    const double* __restrict__ E = EDGES ? a.x_edges : nullptr;
     // left edge of the chunk's first bin
     double za[G1], Ea[G1], ea[G1];
-    double xa = E ? E[i0] : fma(static_cast<double>(i0), a.hx, a.x0);
+    double xa = EDGES ? E[i0] : fma(static_cast<double>(i0), a.hx, a.x0);
     {
       const double x = xa;
 #pragma unroll
@@ -86,8 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
     }
     for (int k = 0; k < len; ++k) {
       const int64_t i = i0 + k;
-      const double xb = E ? E[i + 1] : fma(static_cast<double>(i + 1), a.hx, a.x0);
-      const double ih = E ? 1.0 / (xb - xa) : invh;
+      const double xb = EDGES ? E[i + 1] : fma(static_cast<double>(i + 1), a.hx, a.x0);
+      const double ih = EDGES ? 1.0 / (xb - xa) : invh;
       double mu = 0.0;
       double J[P];
 #pragma unroll
@@ -108,9 +110,9 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
         ea[g] = eb;
       }
       if constexpr (BKG == BKG_EXP) {
-        const double xc = E ? 0.5 * (xa + xb) : fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
+        const double xc = EDGES ? 0.5 * (xa + xb) : fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
         const double tc = (xc - M.tshift) * M.ta;
-        const double dh = E ? 0.5 * (xb - xa) * M.ta : d;
+        const double dh = EDGES ? 0.5 * (xb - xa) * M.ta : d;
         const double Ec = exp_fast(fma(M.c[1], tc, M.c[0]));
         double Sh, dSh;
         sinhc(M.c[1] * dh, Sh, dSh);
@@ -121,9 +123,9 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
           J[3 * NG + 1] = Ec * fma(tc, Sh, dh * dSh);
         }
       } else if constexpr (S::NB > 0) {
-        const double xc = E ? 0.5 * (xa + xb) : fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
+        const double xc = EDGES ? 0.5 * (xa + xb) : fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
         const double tc = (xc - M.tshift) * M.ta;
-        const double dh = E ? 0.5 * (xb - xa) * M.ta : d;
+        const double dh = EDGES ? 0.5 * (xb - xa) * M.ta : d;
         const double d2 = dh * dh;
         double avg[4];
         avg[0] = 1.0;
@@ -280,44 +282,50 @@ LaunchFn pick_edges_ng(int bkg, int obj, bool grad) {
   }
 }
 
-template <int NG, int BKG, int OBJ, bool GRAD>
+template <int NG, int BKG, int OBJ, bool GRAD, bool EDGES>
 hipError_t launch_1d_avg(const NllArgs& a, int grid, hipStream_t s, int* occ) {
-  return launch_or_occupancy(k_nll_1d_avg<NG, BKG, OBJ, GRAD>, a, grid, s, occ);
+  return launch_or_occupancy(k_nll_1d_avg<NG, BKG, OBJ, GRAD, EDGES>, a, grid, s, occ);
 }
 
-template <int NG, int BKG>
-LaunchFn pick_avg_obj(int obj, bool grad) {
+template <int NG, int BKG, bool EDGES>
+LaunchFn pick_avg_obj_e(int obj, bool grad) {
   switch (obj) {
     case OBJ_NEYMAN:
-      return grad ? &launch_1d_avg<NG, BKG, OBJ_NEYMAN, true> : &launch_1d_avg<NG, BKG, OBJ_NEYMAN, false>;
+      return grad ? &launch_1d_avg<NG, BKG, OBJ_NEYMAN, true, EDGES>
+                  : &launch_1d_avg<NG, BKG, OBJ_NEYMAN, false, EDGES>;
     case OBJ_PEARSON:
-      return grad ? &launch_1d_avg<NG, BKG, OBJ_PEARSON, true>
-                  : &launch_1d_avg<NG, BKG, OBJ_PEARSON, false>;
+      return grad ? &launch_1d_avg<NG, BKG, OBJ_PEARSON, true, EDGES>
+                  : &launch_1d_avg<NG, BKG, OBJ_PEARSON, false, EDGES>;
     case OBJ_POISSON:
-      return grad ? &launch_1d_avg<NG, BKG, OBJ_POISSON, true>
-                  : &launch_1d_avg<NG, BKG, OBJ_POISSON, false>;
+      return grad ? &launch_1d_avg<NG, BKG, OBJ_POISSON, true, EDGES>
+                  : &launch_1d_avg<NG, BKG, OBJ_POISSON, false, EDGES>;
     default:
       return nullptr;
   }
 }
 
+template <int NG, int BKG>
+LaunchFn pick_avg_obj(int obj, bool grad, bool edges) {
+  return edges ? pick_avg_obj_e<NG, BKG, true>(obj, grad) : pick_avg_obj_e<NG, BKG, false>(obj, grad);
+}
+
 // bkg: the background code (polynomial degree -1..3, or BKG_EXP).
 template <int NG>
-LaunchFn pick_avg_ng(int bkg, int obj, bool grad) {
+LaunchFn pick_avg_ng(int bkg, int obj, bool grad, bool edges) {
   switch (bkg) {
     case -1:
       if constexpr (NG == 0) return nullptr;
-      else return pick_avg_obj<NG, BKG_NONE>(obj, grad);
+      else return pick_avg_obj<NG, BKG_NONE>(obj, grad, edges);
     case 0:
-      return pick_avg_obj<NG, 0>(obj, grad);
+      return pick_avg_obj<NG, 0>(obj, grad, edges);
     case 1:
-      return pick_avg_obj<NG, 1>(obj, grad);
+      return pick_avg_obj<NG, 1>(obj, grad, edges);
     case 2:
-      return pick_avg_obj<NG, 2>(obj, grad);
+      return pick_avg_obj<NG, 2>(obj, grad, edges);
     case 3:
-      return pick_avg_obj<NG, 3>(obj, grad);
+      return pick_avg_obj<NG, 3>(obj, grad, edges);
     case BKG_EXP:
-      return pick_avg_obj<NG, BKG_EXP>(obj, grad);
+      return pick_avg_obj<NG, BKG_EXP>(obj, grad, edges);
     default:
       return nullptr;
   }
@@ -329,10 +337,10 @@ LaunchFn pick_edges_ng1(int bkg, int obj, bool grad);
 LaunchFn pick_edges_ng2(int bkg, int obj, bool grad);
 LaunchFn pick_edges_ng3(int bkg, int obj, bool grad);
 LaunchFn pick_edges_ng4(int bkg, int obj, bool grad);
-LaunchFn pick_avg_ng0(int bkg, int obj, bool grad);
-LaunchFn pick_avg_ng1(int bkg, int obj, bool grad);
-LaunchFn pick_avg_ng2(int bkg, int obj, bool grad);
-LaunchFn pick_avg_ng3(int bkg, int obj, bool grad);
-LaunchFn pick_avg_ng4(int bkg, int obj, bool grad);
+LaunchFn pick_avg_ng0(int bkg, int obj, bool grad, bool edges);
+LaunchFn pick_avg_ng1(int bkg, int obj, bool grad, bool edges);
+LaunchFn pick_avg_ng2(int bkg, int obj, bool grad, bool edges);
+LaunchFn pick_avg_ng3(int bkg, int obj, bool grad, bool edges);
+LaunchFn pick_avg_ng4(int bkg, int obj, bool grad, bool edges);
 
 }  // namespace hf
