@@ -117,3 +117,25 @@ def test_full_2048_backward_vs_oracle(hf, orc):
     n = case["counts"].reshape(-1).astype(np.float64)
     tol = 4e-7 * np.abs(ref.ell) + 1e-14 * (np.abs(mu.reshape(-1)) + n)
     assert np.all(np.abs(gw - ref.ell) <= tol + 1e-30)
+
+
+@pytest.mark.parametrize("avg", [0, 1])
+def test_gradcheck_bin_average_and_edges(hf, avg):
+    """The same backward through the bin-average model and through bins of
+    any widths (explicit edges), Gauss + exponential background."""
+    import math
+    import torch
+    from paper_2203_06139_amd.autograd import hist_nll
+    spec = dict(datagen.model_spec(2, 1, -1, 0.0, 1.0), bin_average=avg)
+    th = [500.0, 0.45, 0.05, math.log(200.0), math.log(0.3)]
+    c = datagen.random_1d_case(datagen.model_spec(2, 1, -1), 301, 0.0, 1.0, th, 5)
+    counts = torch.as_tensor(c["counts"].view(np.int32), device="cuda")
+    theta = torch.tensor(c["theta_eval"], dtype=torch.float64, device="cuda", requires_grad=True)
+    m = hf.Model.from_spec(spec)
+    w = np.exp(np.random.default_rng(3).uniform(np.log(0.1), 0.0, 301))
+    e = np.concatenate([[0.0], np.cumsum(w)])
+    edges = torch.tensor(e / e[-1], dtype=torch.float64, device="cuda")
+    for ed in (None, edges):
+        assert torch.autograd.gradcheck(
+            lambda t: hist_nll(t, counts, m, (0.0, 1.0), edges=ed), (theta,), eps=1e-6,
+            atol=1e-6, rtol=1e-5)
