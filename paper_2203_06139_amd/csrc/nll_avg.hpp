@@ -86,9 +86,20 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
         ea[g] = exp_fast(-0.5 * za[g] * za[g]);
       }
     }
+    // the next bin's count, weight and right edge are requested while the
+    // current bin is computed (one bin's latency hidden behind its erfs)
+    double n_nx = load_count1(a, i0);
+    double w_nx = a.weights ? static_cast<double>(a.weights[i0]) : 1.0;
+    double xb_nx = EDGES ? E[i0 + 1] : 0.0;
     for (int k = 0; k < len; ++k) {
       const int64_t i = i0 + k;
-      const double xb = EDGES ? E[i + 1] : fma(static_cast<double>(i + 1), a.hx, a.x0);
+      const double n = n_nx, w = w_nx;
+      const double xb = EDGES ? xb_nx : fma(static_cast<double>(i + 1), a.hx, a.x0);
+      if (k + 1 < len) {
+        n_nx = load_count1(a, i + 1);
+        w_nx = a.weights ? static_cast<double>(a.weights[i + 1]) : 1.0;
+        if (EDGES) xb_nx = E[i + 2];
+      }
       const double ih = EDGES ? 1.0 / (xb - xa) : invh;
       double mu = 0.0;
       double J[P];
@@ -138,8 +149,6 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
           if constexpr (GRAD) J[3 * NG + j] = avg[j];
         }
       }
-      const double n = load_count1(a, i);
-      const double w = a.weights ? static_cast<double>(a.weights[i]) : 1.0;
       double l, ub;
       flags |= objective_t<OBJ, false>(n, mu, lut, l, ub) ? ST_DOMAIN : 0;
       acc[0] = fma(w, l, acc[0]);
@@ -182,8 +191,24 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_edges(NllArgs a) {
   const int64_t nb = a.nx;
   const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  // the next grid-stride bin's edges, count and weight are requested while
+  // the current bin is computed
+  double ea_nx = 0.0, eb_nx = 0.0, n_nx = 0.0, w_nx = 1.0;
+  if (tid < nb) {
+    ea_nx = E[tid];
+    eb_nx = E[tid + 1];
+    n_nx = load_count1(a, tid);
+    w_nx = a.weights ? static_cast<double>(a.weights[tid]) : 1.0;
+  }
   for (int64_t i = tid; i < nb; i += stride) {
-    const double x = 0.5 * (E[i] + E[i + 1]);
+    const double x = 0.5 * (ea_nx + eb_nx);
+    const double n = n_nx, w = w_nx;
+    if (i + stride < nb) {
+      ea_nx = E[i + stride];
+      eb_nx = E[i + stride + 1];
+      n_nx = load_count1(a, i + stride);
+      w_nx = a.weights ? static_cast<double>(a.weights[i + stride]) : 1.0;
+    }
     double mu = 0.0;
     double J[P];
 #pragma unroll
@@ -221,8 +246,6 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_edges(NllArgs a) {
         }
       }
     }
-    const double n = load_count1(a, i);
-    const double w = a.weights ? static_cast<double>(a.weights[i]) : 1.0;
     double l, ub;
     flags |= objective_t<OBJ, false>(n, mu, lut, l, ub) ? ST_DOMAIN : 0;
     acc[0] = fma(w, l, acc[0]);
