@@ -170,11 +170,33 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
 // Centre model on bins of any widths: mu at each bin's midpoint, with the
 // closed-form partials (A: e; m: G z; s: G z^2, the 1/s applied to the
 // totals; polynomial t^j; exponential E and t E), one exp per Gaussian.
+// A thread takes kEdgeChunk consecutive bins per step (their kEdgeChunk + 1
+// edges are shared between neighbours), computed together so that their
+// exp chains interleave, and requests the next step's edges, counts and
+// weights while the current step is computed.
+constexpr int kEdgeChunk = 4;
+
+struct EdgeChunk {
+  double e[kEdgeChunk + 1], n[kEdgeChunk], w[kEdgeChunk];
+};
+
+__device__ __forceinline__ void load_edge_chunk(const NllArgs& a, int64_t i0, int len,
+                                                EdgeChunk& c) {
+#pragma unroll
+  for (int k = 0; k <= kEdgeChunk; ++k) c.e[k] = k <= len ? a.x_edges[i0 + k] : 0.0;
+#pragma unroll
+  for (int k = 0; k < kEdgeChunk; ++k) {
+    c.n[k] = k < len ? load_count1(a, i0 + k) : 0.0;
+    c.w[k] = (k < len && a.weights) ? static_cast<double>(a.weights[i0 + k]) : (k < len ? 1.0 : 0.0);
+  }
+}
+
 template <int NG, int BKG, int OBJ, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_nll_1d_edges(NllArgs a) {
   using S = Shape1D<NG, BKG>;
   constexpr int P = S::P;
   constexpr int NV = GRAD ? P + 1 : 1;
+  constexpr int K = kEdgeChunk;
   __shared__ double2 lut[OBJ == OBJ_POISSON ? kLogLut : 1];
   if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
   Model1D<NG, BKG> M;
@@ -187,74 +209,78 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_edges(NllArgs a) {
   const double gseed = a.seed ? a.seed[0] : 1.0;
   const double seed = a.grad_w_out ? gseed : 1.0;
   const bool finite = all_finite(a.theta, a.P);
-  const double* __restrict__ E = a.x_edges;
   const int64_t nb = a.nx;
+  const int64_t nch = (nb + K - 1) / K;
   const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  // the next grid-stride bin's edges, count and weight are requested while
-  // the current bin is computed
-  double ea_nx = 0.0, eb_nx = 0.0, n_nx = 0.0, w_nx = 1.0;
-  if (tid < nb) {
-    ea_nx = E[tid];
-    eb_nx = E[tid + 1];
-    n_nx = load_count1(a, tid);
-    w_nx = a.weights ? static_cast<double>(a.weights[tid]) : 1.0;
+  EdgeChunk nxt;
+  if (tid < nch) {
+    const int64_t i0 = tid * K;
+    load_edge_chunk(a, i0, static_cast<int>(nb - i0 < K ? nb - i0 : K), nxt);
   }
-  for (int64_t i = tid; i < nb; i += stride) {
-    const double x = 0.5 * (ea_nx + eb_nx);
-    const double n = n_nx, w = w_nx;
-    if (i + stride < nb) {
-      ea_nx = E[i + stride];
-      eb_nx = E[i + stride + 1];
-      n_nx = load_count1(a, i + stride);
-      w_nx = a.weights ? static_cast<double>(a.weights[i + stride]) : 1.0;
+  for (int64_t c = tid; c < nch; c += stride) {
+    const EdgeChunk cur = nxt;
+    const int64_t i0 = c * K;
+    const int len = static_cast<int>(nb - i0 < K ? nb - i0 : K);
+    if (c + stride < nch) {
+      const int64_t j0 = (c + stride) * K;
+      load_edge_chunk(a, j0, static_cast<int>(nb - j0 < K ? nb - j0 : K), nxt);
     }
-    double mu = 0.0;
-    double J[P];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      const double z = (x - M.m[g]) * M.is[g];
-      const double e = exp_fast(-0.5 * z * z);
-      const double G = M.A[g] * e;
-      mu += G;
-      if constexpr (GRAD) {
-        const double Gz = G * z;
-        J[3 * g] = e;
-        J[3 * g + 1] = Gz;
-        J[3 * g + 2] = Gz * z;
-      }
-    }
-    const double t = (x - M.tshift) * M.ta;
-    if constexpr (BKG == BKG_EXP) {
-      const double Eb = exp_fast(fma(M.c[1], t, M.c[0]));
-      mu += Eb;
-      if constexpr (GRAD) {
-        J[3 * NG] = Eb;
-        J[3 * NG + 1] = t * Eb;
-      }
-    } else if constexpr (S::NB > 0) {
-      double b = M.c[S::NB - 1];
+    for (int k = 0; k < K; ++k) {
+      const bool in = k < len;
+      // bins past len (the last chunk) are computed at a valid point and
+      // masked: their weight is 0 and their terms are dropped
+      const double x = in ? 0.5 * (cur.e[k] + cur.e[k + 1]) : cur.e[0];
+      double mu = 0.0;
+      double J[P];
 #pragma unroll
-      for (int j = S::NB - 2; j >= 0; --j) b = fma(b, t, M.c[j]);
-      mu += b;
-      if constexpr (GRAD) {
-        double tj = 1.0;
-#pragma unroll
-        for (int j = 0; j < S::NB; ++j) {
-          J[3 * NG + j] = tj;
-          tj *= t;
+      for (int g = 0; g < NG; ++g) {
+        const double z = (x - M.m[g]) * M.is[g];
+        const double e = exp_fast(-0.5 * z * z);
+        const double G = M.A[g] * e;
+        mu += G;
+        if constexpr (GRAD) {
+          const double Gz = G * z;
+          J[3 * g] = e;
+          J[3 * g + 1] = Gz;
+          J[3 * g + 2] = Gz * z;
         }
       }
-    }
-    double l, ub;
-    flags |= objective_t<OBJ, false>(n, mu, lut, l, ub) ? ST_DOMAIN : 0;
-    acc[0] = fma(w, l, acc[0]);
-    if constexpr (GRAD) {
-      const double mb = w * ub;
+      const double t = (x - M.tshift) * M.ta;
+      if constexpr (BKG == BKG_EXP) {
+        const double Eb = exp_fast(fma(M.c[1], t, M.c[0]));
+        mu += Eb;
+        if constexpr (GRAD) {
+          J[3 * NG] = Eb;
+          J[3 * NG + 1] = t * Eb;
+        }
+      } else if constexpr (S::NB > 0) {
+        double b = M.c[S::NB - 1];
 #pragma unroll
-      for (int p = 0; p < P; ++p) acc[1 + p] = fma(mb, J[p], acc[1 + p]);
+        for (int j = S::NB - 2; j >= 0; --j) b = fma(b, t, M.c[j]);
+        mu += b;
+        if constexpr (GRAD) {
+          double tj = 1.0;
+#pragma unroll
+          for (int j = 0; j < S::NB; ++j) {
+            J[3 * NG + j] = tj;
+            tj *= t;
+          }
+        }
+      }
+      double l, ub;
+      const bool dom = objective_t<OBJ, false>(cur.n[k], mu, lut, l, ub);
+      flags |= (dom && in) ? ST_DOMAIN : 0;
+      l = in ? l : 0.0;
+      acc[0] = fma(cur.w[k], l, acc[0]);
+      if constexpr (GRAD) {
+        const double mb = in ? cur.w[k] * ub : 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[1 + p] = fma(mb, J[p], acc[1 + p]);
+      }
+      if (in && a.grad_w_out) a.grad_w_out[i0 + k] = static_cast<float>(seed * l);
     }
-    if (a.grad_w_out) a.grad_w_out[i] = static_cast<float>(seed * l);
   }
   __shared__ double tot[NV];
   __shared__ int totf;
