@@ -60,7 +60,13 @@ __device__ __forceinline__ void gradmap_one(const GradMapArgs& a, int64_t i, dou
 // its first element is computed (a thread streams 16-32 bytes per element
 // for about 40 FP64 operations, so the loads' latency, not the arithmetic,
 // sets the pace).
-constexpr int kPairs = 4;
+// Measured on 2^27 elements (listing configuration / every input and output
+// per element): 8 pairs 837 / 1579 us, 4 pairs 950 / 1654 us, 2 pairs
+// 820 / 1673 us.
+#ifndef HF_GM_PAIRS
+#define HF_GM_PAIRS 8
+#endif
+constexpr int kPairs = HF_GM_PAIRS;
 
 // Non-temporal loads and stores (each element is touched once): measured on
 // 2^27 elements, 937 vs 997 us for the listing's configuration, 1653 vs 1682
