@@ -55,9 +55,15 @@
  * the start instead of the identity, so the first step is a Gauss-Newton
  * (Fisher scoring) step; the eq. 6.20 scaling is then skipped.
  *
- * The MLP routines (or_mlp_*) are the plain forward and backward passes of a
- * dense GELU network with bfloat16 rounding applied at stated points; they
- * check the learned-initialiser kernels.
+ * Further definitions, each written out where it is defined: the expected
+ * Hessian (or_fisher); the bin-average form of the 1D models (the model's
+ * integral over each bin divided by its width, selected by
+ * or_model.bin_average); bins of any widths (or_nll_grad_edges); and the
+ * extended unbinned NLL of single events (or_unbinned).
+ *
+ * The learned initialiser's network is checked by a separate numpy oracle
+ * (mlp.py beside this file): the plain forward and backward passes of a
+ * dense GELU network with bfloat16 rounding applied at stated points.
  *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -std=c11 -shared -fPIC
  */
