@@ -106,8 +106,9 @@ typedef struct {
   int32_t bin_average; /* 0: mu_i is the model at the centre of bin i;
                           1: its average over bin i (integral / width):
                           erf differences per Gaussian, exact averages of
-                          t^j; HF_GAUSS_POLY with nll_eval / nll_grad in
-                          HF_FP64 only, HF_EUNSUPPORTED elsewhere         */
+                          t^j and of exp(b0 + b1 t); 1D models with
+                          nll_eval / nll_grad in HF_FP64 only,
+                          HF_EUNSUPPORTED elsewhere                       */
   double t_shift;      /* background variable t = (x - t_shift)/t_scale   */
   double t_scale;      /* nonzero                                         */
 } hf_model;
@@ -174,7 +175,7 @@ int nll_grad(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t ob
 /* Extended unbinned NLL and its reverse-mode gradient: the binned
  * objective's per-bin evaluation applied to single events at arbitrary
  * positions (the per-event batch evaluation of RooFit-style likelihoods the
- * paper's outlook names, sec. 5).  The HF_GAUSS_POLY model is read as an
+ * paper's outlook names, sec. 5).  A 1D model is read as an
  * intensity lambda(x; theta) (events per unit x):
  *   L(theta) = Lambda(theta) - sum_e w_e ln lambda(x_e),
  *   Lambda   = integral of lambda over [lo, hi] (closed form through erf),
@@ -189,7 +190,7 @@ int nll_grad(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t ob
  *   status_out device i32[1] or NULL: HF_ST_DOMAIN when lambda <= 0 at an
  *              event inside the range (L = +inf, gradient NaN),
  *              HF_ST_NONFINITE when theta is not finite (outputs NaN).
- * Only HF_GAUSS_POLY models (HF_EUNSUPPORTED otherwise).  Uses the
+ * 1D models only (HF_EUNSUPPORTED for HF_GAUSS2D).  Uses the
  * context's reduction scratch: calls on one context must not overlap.     */
 int nll_unbinned(hf_ctx* ctx, const double* events, const float* weights, int64_t n_events,
                  double lo, double hi, const hf_model* model, const double* theta,
