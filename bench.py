@@ -13,6 +13,18 @@ stream the kernels run on.  One JSON line is printed.
 
 The CPU baseline times the FP64 oracle (test infrastructure) on the host on
 one full histogram, repeated for ~10 s.
+
+The same line also carries the metric's second half (unless --hot-only):
+  fits        4096 uneven histograms fitted by one autotuned, graph-replayed
+              fit_batch launch from the plain method's starts; fits/s agreeing
+              with the FP64-bin fit within 1e-6, and the oracle's fitter on
+              the host as its CPU baseline;
+  learned     the learned initialiser trained on --train-fits plain fits, then
+              plain vs learned starts on that batch at the same launch shape
+              (HIP events, median of 5); a learned fit counts only where its
+              NLL is within 1e-6 of the plain fit's;
+  single_fit  the 10,000-bin single fit, 200 fixed BFGS iterations, Poisson
+              and Neyman, beside the oracle's fitter.
 """
 from __future__ import annotations
 
@@ -161,6 +173,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32bin"], default="fp64")
     ap.add_argument("--objective", choices=["poisson", "neyman", "pearson"], default="poisson")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hot-only", action="store_true",
+                    help="default workload: time the 1e7-bin NLL + gradient only, without the "
+                         "fits, learned-initialiser and single-fit sections")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--train-fits", type=int, default=1_000_000,
                     help="learned workload: plain fits the initialiser is trained on")
@@ -343,6 +358,20 @@ def main():
         err_grad = float(np.max(np.abs(g_grad - ref.grad) / ref.scales[1:]))
         result["parity"] = dict(rel_err_nll=err_nll, rel_err_grad=err_grad, tol=tol,
                                 ok=bool(err_nll <= tol and err_grad <= tol))
+        result["cpu_baseline"]["host"] = host_cpu()
+    if not args.hot_only:
+        # the metric's second half: fits/s of the batched fitter, plain vs
+        # learned starts, and the single plain fit
+        log("fits section")
+        fits, batch = fits_section(hf, datagen, np, torch, dev, hf.FP32_BIN, args.steps,
+                                   cpu=not args.no_cpu_baseline)
+        result["fits"] = fits
+        log("learned section")
+        result["learned"] = learned_section(hf, np, torch, dev, batch, args.train_fits,
+                                            args.epochs)
+        log("single-fit section")
+        result["single_fit"] = single_fit_section(hf, datagen, np, torch, dev,
+                                                  cpu=not args.no_cpu_baseline)
     print(json.dumps(result), flush=True)
 
 
@@ -659,11 +688,44 @@ def bench_gradient(args, hf, datagen, np, torch, dev):
         sweep=rows, per_call=per_call)), flush=True)
 
 
-def bench_fits(args, hf, datagen, np, torch, dev):
+def host_cpu():
+    """Host CPU model (from /proc/cpuinfo) and the host's logical CPU count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(model=model, logical_cpus=os.cpu_count(),
+                usable_cpus=len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                else os.cpu_count())
+
+
+def event_time(torch, fn, trials):
+    """Median over `trials` of fn()'s elapsed time between HIP events on the
+    current stream (host synchronisations inside fn are part of it); returns
+    (median ms, all trials)."""
+    out = []
+    for _ in range(trials):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return sorted(out)[len(out) // 2], out
+
+
+def fits_section(hf, datagen, np, torch, dev, prec, steps, cpu=True):
     """4096 histograms (256..65536 bins, Gauss + exponential background) fitted
-    from the default starts in one fit_batch launch (Fisher-started BFGS);
-    fits/s counts fits whose final NLL agrees with the FP64-bin fit from the
-    same start within 1e-6."""
+    from the default starts in one graph-replayed fit_batch launch at the
+    autotuned shape; fits/s counts fits whose final NLL agrees with the
+    FP64-bin fit from the same start within 1e-6.  Returns (section dict,
+    batch data reused by the learned section)."""
     c = datagen.batch_case()
     B = len(c["nbins"])
     counts = torch.from_numpy(c["counts"].view(np.int32)).to(dev)
@@ -672,85 +734,152 @@ def bench_fits(args, hf, datagen, np, torch, dev):
     m = hf.Model.from_spec(c["spec"])
     # the plain method's own starting points (computed once, outside the timing)
     t0 = hf.default_starts(counts, off, rg, m)
-    prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
     from paper_2203_06139_amd.autotune import tune_fit
     # tuned on the whole batch: its longest fits decide the wall time, and a
     # random sample can miss them
-    best, _ = tune_fit(counts, off, rg, m, t0, precision=prec, sample=B, use_cache=False, log=log)
+    best, _ = tune_fit(counts, off, rg, m, t0, precision=prec, sample=B, use_cache=False)
     log("autotuned: %s" % best)
     kw = dict(objective=hf.POISSON, precision=prec, polish_edm=best["polish_edm"])
     ref = hf.fit_batch(counts, off, rg, m, t0, objective=hf.POISSON, precision=hf.FP64)
     out = hf.fit_batch(counts, off, rg, m, t0, **kw)
     torch.cuda.synchronize()
-    steps = max(1, min(args.steps, 5))
+    steps = max(1, min(steps, 5))
     ms = time_graph(torch, lambda k: hf.fit_batch(counts, off, rg, m, t0, out=out, **kw), steps)
-    ok = ((out.status == 0) & (ref.status == 0) & ((out.nll - ref.nll).abs() < 1e-6)).sum().item()
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = fits_cpu_baseline(c, t0.cpu().numpy(), np)
-    print(json.dumps(dict(metric="fits/s at |dNLL|<1e-6", value=ok / (ms * 1e-3), unit="fits/s",
-                          n_gpus=1, steps=steps, warmup=1, ms_per_step=ms, higher_is_better=True,
-                          scaling="weak", vs_baseline=None,
-                          dtype="f64" if prec == hf.FP64 else "f32-bin/f64-acc",
-                          data="synthetic",
-                          config=dict(workload="4096 1D histograms, 256..65536 bins (log-uniform), "
-                                               "Gauss + exponential background, Poisson, default "
-                                               "starts, one fit_batch launch", histograms=B,
-                                      total_bins=int(c["offsets"][-1]), agreeing=ok,
-                                      mean_iters=float(out.iters.float().mean().item()),
-                                      mean_evals=float(out.nevals.float().mean().item()),
-                                      precision=args.precision, tuning=best),
-                          cpu_baseline=cpu)), flush=True)
+    ok = int(((out.status == 0) & (ref.status == 0) & ((out.nll - ref.nll).abs() < 1e-6))
+             .sum().item())
+    sec = dict(metric="fits/s at |dNLL|<1e-6", value=ok / (ms * 1e-3), unit="fits/s",
+               ms_per_batch=ms, steps=steps,
+               dtype="f64" if prec == hf.FP64 else "f32-bin/f64-acc",
+               config=dict(workload="4096 1D histograms, 256..65536 bins (log-uniform), Gauss + "
+                                    "exponential background, Poisson, default starts, one "
+                                    "graph-replayed fit_batch launch", histograms=B,
+                           total_bins=int(c["offsets"][-1])),
+               agreeing=ok, mean_iters=float(out.iters.float().mean().item()),
+               mean_evals=float(out.nevals.float().mean().item()),
+               max_evals=int(out.nevals.max().item()), tuning=best, cpu_baseline=None)
+    if cpu:
+        log("cpu baseline (oracle fits)")
+        sec["cpu_baseline"] = fits_cpu_baseline(c, t0.cpu().numpy(), np)
+    return sec, dict(c=c, counts=counts, off=off, rg=rg, tuning=best)
+
+
+def learned_section(hf, np, torch, dev, batch, train_fits, epochs, trials=5):
+    """The learned initialiser: trained on `train_fits` plain fits of 4096-bin
+    histograms (seeds disjoint from the batch), then the 4096-histogram batch
+    fitted both ways at the same (tuned) launch shape and polish threshold:
+      plain   = default starts + fit_batch,
+      learned = 256-bin rebin + network + fit_batch + plain refit of the fits
+                that did not reach a physical minimum.
+    Each path is timed with HIP events, median of `trials`.  A learned fit
+    agrees when both converged and |NLL_learned - NLL_plain| < 1e-6; fits
+    that reached a lower or a higher minimum are reported apart and do not
+    count."""
+    from paper_2203_06139_amd.learned_init import FitSet, LearnedInit, plain_fit, timed
+    pol = batch["tuning"]["polish_edm"]
+    li = LearnedInit(dev, seed=0, batch=1024)
+    kept, t_data = timed(lambda: li.build_training_set(train_fits, seed=10_000, log=log))
+    hist, t_train = timed(lambda: li.train(epochs=epochs, lr=1e-3, log=log))
+    fs = FitSet(batch["counts"], batch["off"], batch["rg"])
+    res = {}
+    plain_run = lambda: res.__setitem__("plain", plain_fit(fs, polish_edm=pol)[1])
+    learned_run = lambda: res.__setitem__("learned", li.fit(fs, polish_edm=pol))
+    plain_run()
+    learned_run()  # warm-up of both paths
+    ms_plain, tr_plain = event_time(torch, plain_run, trials)
+    ms_learned, tr_learned = event_time(torch, learned_run, trials)
+    plain = res["plain"]
+    learned, nfb = res["learned"]
+    both = (plain.status == 0) & (learned.status == 0)
+    dn = learned.nll - plain.nll
+    n_equal = int((both & (dn.abs() < 1e-6)).sum().item())
+    n_lower = int((both & (dn <= -1e-6)).sum().item())
+    n_higher = int((both & (dn >= 1e-6)).sum().item())
+    n_plain = int((plain.status == 0).sum().item())
+    B = int(plain.status.numel())
+    return dict(
+        metric="fits/s at |dNLL|<1e-6 vs the plain fit", unit="fits/s",
+        value=n_equal / (ms_learned * 1e-3),
+        plain=dict(fits_per_s=n_plain / (ms_plain * 1e-3), converged=n_plain, ms=ms_plain,
+                   trials_ms=tr_plain, mean_iters=float(plain.iters.float().mean().item()),
+                   mean_evals=float(plain.nevals.float().mean().item())),
+        learned=dict(fits_per_s_agreeing=n_equal / (ms_learned * 1e-3), agreeing=n_equal,
+                     lower_minimum=n_lower, higher_minimum=n_higher,
+                     not_both_converged=B - int(both.sum().item()), fallbacks=nfb,
+                     ms=ms_learned, trials_ms=tr_learned,
+                     mean_iters=float(learned.iters.float().mean().item()),
+                     mean_evals=float(learned.nevals.float().mean().item())),
+        speedup=(n_equal / ms_learned) / max(n_plain / ms_plain, 1e-30),
+        tuning=batch["tuning"],
+        training=dict(train_fits=train_fits, kept=kept, epochs=epochs,
+                      final_loss=hist[-1], data_seconds=t_data, train_seconds=t_train))
+
+
+def single_fit_section(hf, datagen, np, torch, dev, trials=5, cpu=True):
+    """The plain single fit: 10,000 bins on [0,10], Gauss + line (5
+    parameters), Poisson counts; 200 BFGS iterations (fixed, no early stop)
+    from (8e3, 4.8, 0.6, 45, -1.5), FP64 bins, Poisson NLL and Neyman
+    chi-square; one fit_batch of one histogram (one workgroup), HIP events,
+    median of `trials`.  CPU baseline: the oracle's fitter, same iterations,
+    one thread."""
+    import oracle
+    c = datagen.single_fit_case()
+    m = hf.Model.from_spec(c["spec"])
+    counts = torch.from_numpy(c["counts"].view(np.int32)).to(dev)
+    off = torch.tensor([0, counts.numel()], dtype=torch.int64, device=dev)
+    rg = torch.tensor([c["range"]], dtype=torch.float64, device=dev)
+    th0 = torch.as_tensor(c["theta0"][None, :], dtype=torch.float64, device=dev)
+    spec = c["spec"]
+    om = oracle.Model(spec["kind"], spec["n_gauss"], spec["poly_degree"], spec["t_shift"],
+                      spec["t_scale"])
+    out = {}
+    for name, obj in (("poisson", hf.POISSON), ("neyman", hf.NEYMAN)):
+        kw = dict(objective=obj, precision=hf.FP64, max_iter=200, fixed_iters=True)
+        r = hf.fit_batch(counts, off, rg, m, th0, **kw)
+        ms, tr = event_time(torch, lambda: hf.fit_batch(counts, off, rg, m, th0, out=r, **kw),
+                            trials)
+        d = dict(ms=ms, trials_ms=tr, iters=int(r.iters[0].item()),
+                 evals=int(r.nevals[0].item()), nll=float(r.nll[0].item()),
+                 status=int(r.status[0].item()))
+        if cpu:
+            t = time.perf_counter()
+            orf = oracle.fit(om, obj, c["counts"], c["theta0"], c["range"], max_iter=200,
+                             fixed_iters=True)
+            d["cpu_baseline"] = dict(ms=1e3 * (time.perf_counter() - t), cores=1, kind="oracle",
+                                     iters=orf.iters, evals=orf.nevals, nll=orf.nll,
+                                     sample="one fit, 200 fixed iterations, 1 thread")
+        out[name] = d
+    return dict(config="10,000 bins on [0,10], Gauss + line (5 parameters), 200 fixed BFGS "
+                       "iterations, FP64 bins, one fit_batch of one histogram", **out)
+
+
+def bench_fits(args, hf, datagen, np, torch, dev):
+    prec = hf.FP64 if args.precision == "fp64" else hf.FP32_BIN
+    sec, _ = fits_section(hf, datagen, np, torch, dev, prec, args.steps,
+                          cpu=not args.no_cpu_baseline)
+    cfg = sec.pop("config")
+    cpu = sec.pop("cpu_baseline")
+    print(json.dumps(dict(metric=sec.pop("metric"), value=sec.pop("value"), unit=sec.pop("unit"),
+                          n_gpus=1, steps=sec.pop("steps"), warmup=1,
+                          ms_per_step=sec.pop("ms_per_batch"), higher_is_better=True,
+                          scaling="weak", vs_baseline=None, dtype=sec.pop("dtype"),
+                          data="synthetic", config=dict(cfg, **sec), cpu_baseline=cpu)),
+          flush=True)
 
 
 def bench_learned(args, hf, datagen, np, torch, dev):
-    """fits/s at |dNLL| < 1e-6 of the plain method (default starts) and of
-    the learned initialiser (with plain-start fallback) on the 4096-histogram
-    batch; the initialiser is trained first on --train-fits plain fits of
-    4096-bin histograms from the same distribution (seeds disjoint)."""
-    from paper_2203_06139_amd.learned_init import FitSet, LearnedInit, plain_fit, timed
-    li = LearnedInit(dev, seed=0, batch=1024)
-    (kept, t_data) = timed(lambda: li.build_training_set(args.train_fits, seed=10_000, log=log))
-    (hist, t_train) = timed(lambda: li.train(epochs=args.epochs, lr=1e-3, log=log))
-    c = datagen.batch_case()
-    fs = FitSet(torch.from_numpy(c["counts"].view(np.int32)).to(dev),
-                torch.as_tensor(c["offsets"], device=dev), torch.as_tensor(c["ranges"], device=dev))
-    plain_fit(fs)  # warm-up
-    li.fit(fs)
-    (_, plain), t_plain = timed(lambda: plain_fit(fs))
-    (learned, nfb), t_learned = timed(lambda: li.fit(fs))
-    # the plain fit judges: a learned fit counts if it converged and its final
-    # NLL is within 1e-6 of the plain fit's (equal) or below it by more
-    # (better minimum); the two are also reported apart
-    both = (plain.status == 0) & (learned.status == 0)
-    dn = learned.nll - plain.nll
-    equal = both & (dn.abs() < 1e-6)
-    better = both & (dn <= -1e-6)
-    n_equal = int(equal.sum().item())
-    n_better = int(better.sum().item())
-    n_agree = n_equal + n_better
-    n_plain = int((plain.status == 0).sum().item())
-    B = len(c["nbins"])
+    _, batch = fits_section(hf, datagen, np, torch, dev, hf.FP32_BIN, args.steps, cpu=False)
+    sec = learned_section(hf, np, torch, dev, batch, args.train_fits, args.epochs)
     print(json.dumps(dict(
-        metric="fits/s at |dNLL|<1e-6: plain vs batched+learned init", value=n_agree / t_learned,
-        unit="fits/s", n_gpus=1, steps=1, warmup=1, ms_per_step=1e3 * t_learned,
+        metric="fits/s at |dNLL|<1e-6: plain vs batched+learned init", value=sec["value"],
+        unit="fits/s", n_gpus=1, steps=1, warmup=1, ms_per_step=sec["learned"]["ms"],
         higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32-bin/f64-acc",
         data="synthetic",
-        config=dict(workload="4096 1D histograms, 256..65536 bins, Gauss + exponential background, "
-                             "Poisson; plain = default starts + fit_batch, learned = 256-bin "
-                             "rebin + BF16-MFMA MLP starts + fit_batch + plain fallback",
-                    histograms=B, train_fits=args.train_fits, train_kept=kept,
-                    epochs=args.epochs, final_train_loss=hist[-1]),
-        plain=dict(fits_per_s=n_plain / t_plain, converged=n_plain, seconds=t_plain,
-                   mean_iters=float(plain.iters.float().mean().item()),
-                   mean_evals=float(plain.nevals.float().mean().item())),
-        learned=dict(fits_per_s_agreeing=n_agree / t_learned, agreeing=n_agree, equal=n_equal,
-                     better=n_better, worse=int((both & (dn >= 1e-6)).sum().item()),
-                     seconds=t_learned,
-                     fallbacks=nfb, mean_iters=float(learned.iters.float().mean().item()),
-                     mean_evals=float(learned.nevals.float().mean().item())),
-        speedup=(n_agree / t_learned) / max(n_plain / t_plain, 1e-30),
-        training=dict(data_seconds=t_data, train_seconds=t_train))), flush=True)
+        config=dict(workload="4096 1D histograms, 256..65536 bins, Gauss + exponential "
+                             "background, Poisson; plain = default starts + fit_batch, learned "
+                             "= 256-bin rebin + BF16-MFMA MLP starts + fit_batch + plain "
+                             "fallback", histograms=int(batch["off"].numel() - 1)),
+        plain=sec["plain"], learned=sec["learned"], speedup=sec["speedup"],
+        tuning=sec["tuning"], training=sec["training"])), flush=True)
 
 
 if __name__ == "__main__":

@@ -136,10 +136,12 @@ typedef struct {
 
 /* Creates a context on HIP device `device` and makes it current for the
  * calling thread.  The context owns the device scratch used by reductions
- * and fits (per-block partial sums, a completion ticket, fit work queue).
- * Scratch grows on demand and is never freed before hf_ctx_destroy; a call
- * that would grow it while `stream` is being captured returns HF_ECAPTURE
- * (warm the context up with one uncaptured call of the same size first).  */
+ * and fits (per-block partial sums, a completion ticket, the log table, the
+ * fit work queue and the 65,536-entry longest-first ordering buffer).  All
+ * of it is allocated here, once, and freed only by hf_ctx_destroy: no other
+ * call allocates, frees or synchronises, so every call may be captured into
+ * a HIP graph, and a graph captured earlier stays valid after later calls
+ * of any size.  HF_ECAPTURE is reserved; no call returns it.              */
 int hf_ctx_create(hf_ctx** out, int device);
 void hf_ctx_destroy(hf_ctx* ctx);
 /* Message of the last failing call on ctx (empty string if none); valid
@@ -149,7 +151,10 @@ const char* hf_last_error(const hf_ctx* ctx);
 /* Number of parameters P of a model, or HF_EINVAL / HF_EUNSUPPORTED.      */
 int hf_model_nparams(const hf_model* model);
 
-/* NLL value.
+/* NLL value: the fit objective L(theta) = sum_i w_i l(n_i, mu_i(theta))
+ * over every bin, the function whose parameter gradient the paper's
+ * histogram-fitting application differentiates (sec. 4, Fig. 2a: a TH1D
+ * fitted with a TF1 of Gaussians).
  *   theta      device f64[P], read on the device (no host copy).
  *   nll_out    device f64[1], overwritten with L(theta).
  *   status_out device i32[1] or NULL, overwritten with the hf_bin_status
@@ -158,7 +163,12 @@ int nll_eval(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t ob
              int32_t precision, const double* theta, double* nll_out, int32_t* status_out,
              hf_stream_t stream);
 
-/* NLL and its reverse-mode gradient, in one pass over the bins.
+/* NLL and its reverse-mode gradient, in one pass over the bins: the
+ * adjoint of L propagated back through every bin's model evaluation to the
+ * parameters (sec. 2: reverse accumulation costs a small multiple of one
+ * function evaluation whatever P is; sec. 3: reads of theta shared by all
+ * bins become adjoint writes by all bins, summed here in a fixed order;
+ * Listing 1: the caller supplies the storage the adjoints are written to).
  *   seed       device f64[1] upstream adjoint dOut/dL, or NULL for 1.
  *   nll_out    device f64[1], overwritten with L(theta) (not scaled by seed).
  *   grad_out   device f64[P], OVERWRITTEN (not accumulated) with
@@ -298,7 +308,12 @@ typedef enum {
   HF_FIT_BADHIST = 5 /* offsets[b+1] <= offsets[b] or a bad range        */
 } hf_fit_status;
 
-/* Fits B independent 1D histograms in one launch.
+/* Fits B independent 1D histograms in one launch: the paper's histogram
+ * fit (sec. 4, Fig. 2a and 2b: a gradient-driven minimisation of the fit
+ * objective, the gradient taken by reverse mode or, for comparison, by
+ * central differences) repeated over a batch, one persistent workgroup per
+ * fit at a time.  Batches of up to 65,536 histograms are taken longest
+ * first; larger batches in index order.
  *   counts_concat device array of counts_dtype: histogram b occupies
  *                 [offsets[b], offsets[b+1]).
  *   offsets       device i64[B+1], offsets[0] = 0, nondecreasing.
@@ -360,6 +375,20 @@ int64_t hf_mlp_nparams(void);
 /* Device scratch a forward or training step of `batch` rows needs (bytes);
  * HF_EINVAL (negative) for a batch that is not a positive multiple of 64.  */
 int64_t hf_mlp_workspace_bytes(int32_t batch);
+/* Where a workspace of `batch` rows keeps the network's stored values, as
+ * byte offsets from its start (for inspecting them after a call, e.g. to
+ * check each layer against a reference element by element).  offsets
+ * (host int64[12]) receives, in order:
+ *   a0 a1 a2 a3   BF16 [batch][in_l] layer inputs: a0 = bf16(x), a_l the
+ *                 rounded GELU outputs of hidden layer l;
+ *   z1 z2 z3      FP32 [batch][512] hidden pre-activations (training step
+ *                 only);
+ *   y             FP32 [batch][32] network output (training step only);
+ *   dz1 .. dz4    BF16 [batch][out_l] adjoints of the pre-activations of
+ *                 layers 1..4 (training step only).
+ * Returns 0, or HF_EINVAL for a batch that is not a positive multiple of 64
+ * or a NULL offsets.  Host-only.                                          */
+int hf_mlp_workspace_layout(int32_t batch, int64_t* offsets);
 
 /* Rebins histogram b of counts_concat (offsets as in fit_batch) to 256 coarse
  * bins -- fine bin i goes to coarse bin floor((i + 1/2) 256 / nbins) -- and

@@ -212,18 +212,54 @@ static double centre(double lo, double hi, int64_t n, int64_t i) {
   return lo + ((double)i + 0.5) * h;
 }
 
-/* S(u) = sinh(u)/u and S'(u): the average of exp(b0 + b1 t) over
- * [t_c - d, t_c + d] is exp(b0 + b1 t_c) S(b1 d).  For |u| < 1/2 the Taylor
- * series to u^10 (truncation below 4e-14 relative); beyond, the closed
- * forms, where cosh u - S(u) no longer cancels badly.                     */
+/* S(u) = sinh(u)/u and S'(u), from their definition as averages over
+ * s in [-1, 1]:  S(u) = (1/2) int e^{u s} ds,  S'(u) = (1/2) int s e^{u s} ds.
+ * The average of exp(b0 + b1 t) over [t_c - d, t_c + d] is
+ * exp(b0 + b1 t_c) S(b1 d).  For |u| < 1 the two integrals are taken by
+ * 16-point Gauss-Legendre quadrature (exact to rounding for these entire
+ * integrands: the rule integrates polynomials of degree 31), pairing the
+ * nodes +-x so that the sums are of cosh(u x) and x sinh(u x), positive
+ * terms with no cancellation; for |u| >= 1 by the closed forms sinh(u)/u and
+ * (u cosh u - sinh u)/u^2, which no longer cancel badly there.            */
+static double gl_x[8], gl_w[8]; /* positive Gauss-Legendre nodes, weights */
+
+/* Nodes and weights of the 16-point Gauss-Legendre rule on [-1, 1]: the
+ * roots of the Legendre polynomial P_16 by Newton's method on the
+ * three-term recurrence, w = 2 / ((1 - x^2) P_16'(x)^2).                  */
+__attribute__((constructor)) static void gauss_legendre16(void) {
+  const int n = 16;
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n / 2; ++i) {
+    double z = cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) <= 1e-16) break;
+    }
+    gl_x[i] = z;
+    gl_w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
 static void sinhc(double u, double* S, double* dS) {
-  if (fabs(u) < 0.5) {
-    double u2 = u * u;
-    *S = 1.0 + u2 / 6.0 * (1.0 + u2 / 20.0 * (1.0 + u2 / 42.0 * (1.0 + u2 / 72.0 * (1.0 + u2 / 110.0))));
-    *dS = u / 3.0 * (1.0 + u2 / 10.0 * (1.0 + u2 / 28.0 * (1.0 + u2 / 54.0 * (1.0 + u2 / 88.0))));
+  if (fabs(u) < 1.0) {
+    double s = 0.0, d = 0.0;
+    for (int i = 0; i < 8; ++i) {
+      s += gl_w[i] * cosh(u * gl_x[i]);
+      d += gl_w[i] * gl_x[i] * sinh(u * gl_x[i]);
+    }
+    *S = s;
+    *dS = d;
   } else {
     *S = sinh(u) / u;
-    *dS = (cosh(u) - *S) / u;
+    *dS = (u * cosh(u) - sinh(u)) / (u * u);
   }
 }
 

@@ -89,7 +89,8 @@ class HistfitError(RuntimeError):
 
 
 _lib = None
-_ctx = {}
+_ctx = {}      # (device, stream handle) -> hf_ctx
+_tuning = {}   # device -> (wg_per_cu, cache_bins, block_size) set by fit_set_tuning
 
 
 def load():
@@ -124,6 +125,8 @@ def load():
     L.hf_mlp_nparams.restype = i64
     L.hf_mlp_workspace_bytes.argtypes = [i32]
     L.hf_mlp_workspace_bytes.restype = i64
+    L.hf_mlp_workspace_layout.argtypes = [i32, vp]
+    L.hf_mlp_workspace_layout.restype = ctypes.c_int
     L.hf_rebin_lognorm.argtypes = [vp, i32, vp, i32, vp, f32, f32, vp, vp]
     L.hf_default_starts.argtypes = [vp, i32, vp, i32, vp, vp, ctypes.POINTER(HfModel), vp, vp]
     L.hf_column_stats.argtypes = [vp, i64, i32, vp, vp, vp, vp]
@@ -149,21 +152,32 @@ def load():
     return L
 
 
-def context(device: int | None = None):
-    """The library context of a device (created on first use, kept for the process)."""
+def context(device: int | None = None, stream=None):
+    """The library context of (device, stream): created on first use and kept
+    for the process.  A context's scratch (block partials, completion ticket,
+    fit queue) may only be used by calls that do not overlap, so every stream
+    gets its own: calls serialised on one stream share a context, and calls
+    on different streams (a graph captured on a side stream and eager work on
+    the default stream included) never do.  `stream` defaults to the
+    device's current torch stream."""
     import torch
     L = load()
     if not torch.cuda.is_available():
         raise HistfitError("no GPU visible: the HIP library has no CPU path")
     dev = torch.cuda.current_device() if device is None else int(device)
-    if dev not in _ctx:
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev, int(stream))
+    if key not in _ctx:
         h = ctypes.c_void_p()
         with torch.cuda.device(dev):
             rc = L.hf_ctx_create(ctypes.byref(h), dev)
         if rc != 0:
             raise HistfitError("hf_ctx_create(%d) failed: %d" % (dev, rc))
-        _ctx[dev] = h
-    return _ctx[dev]
+        if dev in _tuning:
+            _check(L.hf_fit_set_tuning(h, *_tuning[dev]), h)
+        _ctx[key] = h
+    return _ctx[key]
 
 
 def _check(rc, ctx):
@@ -282,23 +296,46 @@ def _check_theta(th, model):
 
 
 def _check_hist_sizes(hist: Hist):
+    """Raises unless the histogram's tensors are what the kernels read through
+    plain pointers: contiguous, on one GPU, of the expected dtypes and sizes
+    (counts [nx] or [ny, nx] int32/uint32/f32/f64, weights f32 per bin,
+    edges f64[nx + 1] for 1D)."""
+    import torch
     c = hist.counts
+    if not isinstance(c, torch.Tensor) or c.device.type != "cuda":
+        raise ValueError("counts must be a device tensor")
     if c.dim() not in (1, 2):
         raise ValueError("counts must be [nx] or [ny, nx]")
-    if hist.weights is not None and hist.weights.numel() != c.numel():
-        raise ValueError("weights must have one value per bin")
+    if c.dtype not in (torch.int32, torch.uint32, torch.float32, torch.float64):
+        raise ValueError("counts must be int32/uint32 (read as u32), float32 or float64")
+    if not c.is_contiguous():
+        raise ValueError("counts must be contiguous")
+    if hist.weights is not None:
+        w = hist.weights
+        if not isinstance(w, torch.Tensor) or w.numel() != c.numel():
+            raise ValueError("weights must have one value per bin")
+        _need(w, "weights", torch.float32, c.numel(), c.device)
+    if hist.edges is not None:
+        if c.dim() != 1:
+            raise ValueError("edges are for 1D histograms")
+        _need(hist.edges, "edges", torch.float64, c.numel() + 1, c.device)
+        if hist.edges.numel() != c.numel() + 1:
+            raise ValueError("edges must have nx + 1 values")
 
 
 def nll_eval(hist: Hist, model: Model, theta, objective=POISSON, precision=FP64, out=None,
              status=None):
     """L(theta) as a device f64[1] tensor (and the status word if asked for)."""
     import torch
+    _check_hist_sizes(hist)
     dev = hist.counts.device
     ctx = context(dev.index)
     th = _dev_tensor(theta, torch.float64, dev, "theta")
     _check_theta(th, model)
-    _check_hist_sizes(hist)
     out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    _need(out, "out", torch.float64, 1, dev)
+    if status is not None:
+        _need(status, "status", torch.int32, 1, dev)
     rc = load().nll_eval(ctx, ctypes.byref(hist.c()), ctypes.byref(model.c()), objective,
                          precision, _ptr(th), _ptr(out), _ptr(status), _stream(dev))
     _check(rc, ctx)
@@ -310,21 +347,27 @@ def nll_grad(hist: Hist, model: Model, theta, objective=POISSON, precision=FP64,
              status=None):
     """(L, dL/dtheta * seed, optional seed * dL/dw) as device tensors."""
     import torch
+    _check_hist_sizes(hist)
     dev = hist.counts.device
     ctx = context(dev.index)
     th = _dev_tensor(theta, torch.float64, dev, "theta")
     _check_theta(th, model)
-    _check_hist_sizes(hist)
     P = th.numel()
-    if grad_out is not None and grad_out.numel() < P:
-        raise ValueError("grad_out too small")
     if grad_w_out is not None and grad_w_out.numel() != hist.counts.numel():
         raise ValueError("grad_w_out must have one value per bin")
     nll_out = torch.empty(1, dtype=torch.float64, device=dev) if nll_out is None else nll_out
     grad_out = torch.empty(P, dtype=torch.float64, device=dev) if grad_out is None else grad_out
     if want_grad_w and grad_w_out is None:
         grad_w_out = torch.empty(hist.counts.shape, dtype=torch.float32, device=dev)
+    _need(nll_out, "nll_out", torch.float64, 1, dev)
+    _need(grad_out, "grad_out", torch.float64, P, dev)
+    if grad_w_out is not None:
+        _need(grad_w_out, "grad_w_out", torch.float32, hist.counts.numel(), dev)
+    if status is not None:
+        _need(status, "status", torch.int32, 1, dev)
     sd = None if seed is None else _dev_tensor(seed, torch.float64, dev, "seed")
+    if sd is not None and sd.numel() != 1:
+        raise ValueError("seed must hold one value")
     rc = load().nll_grad(ctx, ctypes.byref(hist.c()), ctypes.byref(model.c()), objective,
                          precision, _ptr(th), _ptr(sd), _ptr(nll_out), _ptr(grad_out),
                          _ptr(grad_w_out), free_mask, _ptr(status), _stream(dev))
@@ -337,16 +380,19 @@ def nll_fisher(hist: Hist, model: Model, theta, objective=POISSON, out=None, sta
     theta as a device f64[P, P] tensor (c_i = 1/mu Poisson, 2/mu Pearson,
     2/n Neyman)."""
     import torch
+    _check_hist_sizes(hist)
     dev = hist.counts.device
     ctx = context(dev.index)
     th = _dev_tensor(theta, torch.float64, dev, "theta")
     _check_theta(th, model)
-    _check_hist_sizes(hist)
     P = th.numel()
     if out is None:
         out = torch.empty((P, P), dtype=torch.float64, device=dev)
-    elif out.numel() != P * P or out.dtype != torch.float64 or not out.is_contiguous():
+    elif out.numel() != P * P:
         raise ValueError("out must be a contiguous f64 tensor of P*P values")
+    _need(out, "out", torch.float64, P * P, dev)
+    if status is not None:
+        _need(status, "status", torch.int32, 1, dev)
     rc = load().hf_nll_fisher(ctx, ctypes.byref(hist.c()), ctypes.byref(model.c()), objective,
                               _ptr(th), _ptr(out), _ptr(status), _stream(dev))
     _check(rc, ctx)
@@ -458,6 +504,8 @@ def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=PO
     differences of the objective, FP64 only)."""
     import torch
     c = counts_concat
+    if not isinstance(c, torch.Tensor) or c.device.type != "cuda" or not c.is_contiguous():
+        raise ValueError("counts_concat must be a contiguous device tensor")
     dev = c.device
     ctx = context(dev.index)
     if not isinstance(offsets, torch.Tensor) or offsets.device.type == "cpu":
@@ -480,6 +528,10 @@ def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=PO
                              torch.empty(B, dtype=torch.int32, device=dev),
                              torch.empty(B, dtype=torch.int32, device=dev),
                              torch.empty(B, dtype=torch.int32, device=dev))
+    _need(out.theta, "out.theta", torch.float64, B * P, dev)
+    _need(out.nll, "out.nll", torch.float64, B, dev)
+    for name in ("status", "iters", "nevals"):
+        _need(getattr(out, name), "out." + name, torch.int32, B, dev)
     opts = HfFitOpts(max_iter, ls_max, 1 if fixed_iters else 0, free_mask, edm_tol, polish_edm,
                      int(hessian_init), int(gradient))
     rc = load().fit_batch(ctx, B, _ptr(c), _dtype_code(c), _ptr(off), _ptr(rg),
@@ -491,13 +543,21 @@ def fit_batch(counts_concat, offsets, ranges, model: Model, theta0, objective=PO
 
 
 def fit_set_tuning(wg_per_cu: int, cache_bins: int, block_size: int = 256, device=None):
-    """fit_batch launch shape of this device's context (see hf_fit_set_tuning)."""
-    ctx = context(device)
-    _check(load().hf_fit_set_tuning(ctx, int(wg_per_cu), int(cache_bins), int(block_size)), ctx)
+    """fit_batch launch shape (see hf_fit_set_tuning) of every context of the
+    device, those of streams first used later included."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    shape = (int(wg_per_cu), int(cache_bins), int(block_size))
+    ctx = context(dev)
+    _check(load().hf_fit_set_tuning(ctx, *shape), ctx)
+    _tuning[dev] = shape
+    for (d, _), h in _ctx.items():
+        if d == dev and h is not ctx:
+            _check(load().hf_fit_set_tuning(h, *shape), h)
 
 
 def fit_get_tuning(device=None):
-    """(wg_per_cu, cache_bins, block_size) of this device's context."""
+    """(wg_per_cu, cache_bins, block_size) of the device's current-stream context."""
     ctx = context(device)
     w, c, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(load().hf_fit_get_tuning(ctx, ctypes.byref(w), ctypes.byref(c), ctypes.byref(b)), ctx)
@@ -527,6 +587,30 @@ def mlp_workspace(batch: int, device):
     if n < 0:
         raise ValueError("batch must be a positive multiple of 64")
     return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def mlp_workspace_views(workspace, batch: int) -> dict:
+    """Views of the values a workspace stores (see hf_mlp_workspace_layout):
+    'a0'..'a3' and 'dz1'..'dz4' as int16 tensors holding BF16 bit patterns,
+    'z1'..'z3' and 'y' as float32, each [batch][columns]."""
+    import torch
+    offs = (ctypes.c_int64 * 12)()
+    rc = load().hf_mlp_workspace_layout(int(batch), offs)
+    if rc != 0:
+        raise ValueError("batch must be a positive multiple of 64")
+    ins = (MLP_IN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN)
+    outs = (MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN, MLP_OUT_PAD)
+    spec = [("a%d" % l, torch.int16, ins[l]) for l in range(4)]
+    spec += [("z%d" % l, torch.float32, MLP_HIDDEN) for l in (1, 2, 3)]
+    spec += [("y", torch.float32, MLP_OUT_PAD)]
+    spec += [("dz%d" % l, torch.int16, outs[l - 1]) for l in (1, 2, 3, 4)]
+    views = {}
+    for (name, dt, cols), o in zip(spec, offs):
+        nbytes = batch * cols * (2 if dt == torch.int16 else 4)
+        if o + nbytes > workspace.numel():
+            raise ValueError("workspace too small for batch %d" % batch)
+        views[name] = workspace[o:o + nbytes].view(dt).view(batch, cols)
+    return views
 
 
 def _batch_args(counts_concat, offsets):

@@ -3,10 +3,12 @@
 Searches the workgroup size (256 or 512 threads) x persistent workgroups per
 CU x the LDS count cache (in bins) x the FP32->FP64 polish threshold by
 timing fit_batch (HIP events) on a sample of the batch to be fitted (the
-whole batch when `sample` is at least its size), keeps the fastest configuration whose fits agree with
-the FP64 fit of the same sample (|dNLL| < 1e-6 where both converge), applies
-it to the context, and caches it as JSON keyed by (GPU arch, CU count, model,
-objective, precision).  Cache file: $HF_AUTOTUNE_CACHE or
+whole batch when `sample` is at least its size), keeps the fastest
+configuration whose fits agree with the FP64 fit of the same sample
+(|dNLL| < 1e-6 where both converge), applies it to the device's contexts, and
+caches it as JSON keyed by (GPU arch, CU count, model, objective, precision).
+When no configuration agrees, the shape in place before the search is
+restored and RuntimeError is raised.  Cache file: $HF_AUTOTUNE_CACHE or
 ~/.cache/histfit/autotune.json.
 """
 from __future__ import annotations
@@ -17,7 +19,8 @@ import os
 
 import torch
 
-from . import FP32_BIN, FP64, POISSON, Model, fit_batch, fit_max_cache_bins, fit_set_tuning
+from . import (FP32_BIN, FP64, POISSON, Model, fit_batch, fit_get_tuning, fit_max_cache_bins,
+               fit_set_tuning)
 
 BLOCKS = (256, 512)
 WG_PER_CU = (1, 2, 4, 8)
@@ -63,6 +66,7 @@ def tune_fit(counts, offsets, ranges, model: Model, theta0, objective=POISSON, p
             c = known[k]
             fit_set_tuning(c["wg_per_cu"], c["cache_bins"], c.get("block_size", 256))
             return c, []
+    before = fit_get_tuning()
     B = offsets.numel() - 1
     g = torch.Generator().manual_seed(seed)
     idx = torch.randperm(B, generator=g)[:min(sample, B)].sort().values
@@ -88,7 +92,11 @@ def tune_fit(counts, offsets, ranges, model: Model, theta0, objective=POISSON, p
                             agree=agree))
         if log:
             log(results[-1])
-    ok = [r for r in results if r["agree"]] or results
+    ok = [r for r in results if r["agree"]]
+    if not ok:
+        fit_set_tuning(*before)
+        raise RuntimeError("no launch shape reproduced the FP64 fits of the sample within 1e-6; "
+                           "the previous shape %r is kept" % (before,))
     best = min(ok, key=lambda r: r["ms"])
     fit_set_tuning(best["wg_per_cu"], best["cache_bins"], best["block_size"])
     if use_cache:

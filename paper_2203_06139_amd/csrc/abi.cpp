@@ -669,6 +669,19 @@ HF_EXPORT int64_t hf_mlp_workspace_bytes(int32_t batch) {
   return hf::mlp_workspace_bytes(batch);
 }
 
+HF_EXPORT int hf_mlp_workspace_layout(int32_t batch, int64_t* offsets) {
+  if (batch < 64 || batch % 64 != 0 || !offsets) return HF_EINVAL;
+  // carve from a fake base far from 0 so every view is a non-null offset
+  char* base = reinterpret_cast<char*>(uintptr_t(1) << 40);
+  const hf::MlpWorkspace w = hf::mlp_carve(base, batch);
+  auto off = [base](const void* p) { return static_cast<int64_t>(static_cast<const char*>(p) - base); };
+  for (int l = 0; l < 4; ++l) offsets[l] = off(w.a[l]);
+  for (int l = 1; l <= 3; ++l) offsets[3 + l] = off(w.z[l]);
+  offsets[7] = off(w.y);
+  for (int l = 1; l <= 4; ++l) offsets[7 + l] = off(w.dz[l]);
+  return HF_OK;
+}
+
 HF_EXPORT int hf_rebin_lognorm(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
                                const int64_t* offsets, float in_mean, float in_std, float* out,
                                hf_stream_t stream) {

@@ -6,11 +6,12 @@
 // r_0 = exp(-dz z_0 - dz^2/2) and D = exp(-dz^2): two exps per Gaussian per
 // chunk instead of one per bin.  An exponential background exp(b0 + b1 t) is
 // a geometric sequence on the grid, E_{k+1} = E_k exp(b1 dt): one exp per
-// chunk.  After k steps the relative error is about
-// k^2/2 ulp.  The recurrence is used only when K |dz| <= 1: then an e_0 that
-// underflows (|z_0| > 38.6) implies every e_k in the chunk is below 1e-300,
-// so nothing that matters is lost; r_0's exponent is clamped to +-700 so
-// that 0 * r_0 stays 0.  Otherwise each bin takes its own exp.
+// chunk.  After k steps the relative error is about k^2/2 ulp.  The
+// recurrence is used only when K |dz| <= 1: then an e_0 that underflows
+// (|z_0| > 38.6) implies every e_k in the chunk is below 1e-300, so nothing
+// that matters is lost; r_0's exponent is clamped (+-700 in FP64, +-80 where
+// the FP32 exp takes it) so that 0 * r_0 stays 0.  Otherwise each bin takes
+// its own exp.
 //
 // Objective terms are branch-free (domain cases are only flagged), so the
 // compiler can interleave the K bins.
@@ -32,14 +33,14 @@ __device__ __forceinline__ bool objective_t(double n, double mu, const double2* 
   constexpr double kTiny = 1e-300;
   if constexpr (OBJ == OBJ_NEYMAN) {
     const bool pos = n > 0.0;
-    const double inv = F32BIN ? rcp_hw32(fmax(n, kTiny)) : rcp_fast(fmax(n, kTiny));
+    const double inv = rcp_fast(fmax(n, kTiny));
     const double d = mu - n;
     const double di = pos ? d * inv : 0.0;
     l = d * di;
     ub = 2.0 * di;
     return false;
   } else if constexpr (OBJ == OBJ_PEARSON) {
-    const double inv = F32BIN ? rcp_hw32(fmax(mu, kTiny)) : rcp_fast(fmax(mu, kTiny));
+    const double inv = rcp_fast(fmax(mu, kTiny));
     const double d = n - mu;
     const double r = n * inv;
     l = d * d * inv;
@@ -70,7 +71,7 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
     z0[g] = (xs - M.m[g]) * M.is[g];
     if constexpr (RECUR) {
       const double q0 = -0.5 * z0[g] * z0[g];
-      const double a0 = fmin(fmax(fma(-M.dz[g], z0[g], -0.5 * M.dz[g] * M.dz[g]), -700.0), 700.0);
+      const double a0 = clamp_ratio_exponent<F32BIN>(fma(-M.dz[g], z0[g], -0.5 * M.dz[g] * M.dz[g]));
       e[g] = F32BIN ? exp_hw32(q0) : exp_fast(q0);
       r[g] = F32BIN ? exp_hw32(a0) : exp_fast(a0);
     }

@@ -12,6 +12,8 @@
 //              correction, which brings the quotient to about 1 ulp (the
 //              refinement the compiler's IEEE division uses, without its
 //              scaling for extreme exponents).
+//   exp_hw32   the FP32 hardware exp2, for the FP32-per-bin variant: results
+//              below about e^-87 are 0 and above e^88 infinite.
 //   log_lut    x = 2^e m, m in [1,2); a 1024-entry LDS table of 1/c_j and
 //              ln c_j at the midpoints c_j of the top 10 mantissa bits gives
 //              f = m/c_j - 1 with |f| < 2^-11, and ln(1+f) is a degree-4
@@ -67,17 +69,22 @@ __device__ __forceinline__ double rcp_fast(double d) {
   return fma(y, fma(-d, y, 1.0), y);
 }
 
-// FP32 reciprocal seed with one FP64 Newton step (about 1e-14 relative).
-__device__ __forceinline__ double rcp_hw32(double d) {
-  const double y = static_cast<double>(__builtin_amdgcn_rcpf(static_cast<float>(d)));
-  return y * fma(-d, y, 2.0);
-}
-
+// a / d for a positive normal d.  The FP32-per-bin variant keeps the FP64
+// seed (an FP32 seed would overflow or vanish for divisors outside FP32's
+// range) and drops the residual correction (2.3e-15 relative is ample there).
 template <bool F32BIN>
 __device__ __forceinline__ double div_fast(double a, double d) {
-  const double y = F32BIN ? rcp_hw32(d) : rcp_fast(d);
+  const double y = rcp_fast(d);
   const double q = a * y;
-  return fma(fma(-d, q, a), y, q);
+  return F32BIN ? q : fma(fma(-d, q, a), y, q);
+}
+
+// Clamp of a recurrence ratio's exponent: 0 * exp(a) must stay 0, so exp(a)
+// must stay finite in the precision it is taken in (e^88.7 overflows FP32).
+template <bool F32BIN>
+__device__ __forceinline__ double clamp_ratio_exponent(double a) {
+  constexpr double lim = F32BIN ? 80.0 : 700.0;
+  return fmin(fmax(a, -lim), lim);
 }
 
 // Log table entry j: 1/c_j and ln of c_j (of c_j/2 from 1.5 up), with

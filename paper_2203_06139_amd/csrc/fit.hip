@@ -6,10 +6,11 @@ namespace hf {
 
 namespace {
 
+constexpr int kMaxRankB = 1 << 16;
+
 // Rank every histogram by size, longest first, ties by index: a strict total
 // order, so the ranks form a permutation.  O(B^2) comparisons staged through
 // LDS tiles; used for B <= kMaxRankB.
-constexpr int kMaxRankB = 1 << 16;
 
 __global__ __launch_bounds__(kBlock) void k_rank_sizes(const int64_t* __restrict__ offsets, int B,
                                                       int32_t* __restrict__ order) {
@@ -50,10 +51,15 @@ FitLaunchFn pick_fit(int ng, int bkg, int obj, int blk) {
 
 }  // namespace
 
+// The ordering buffer is allocated once, for the largest batch that is
+// ranked (kMaxRankB histograms, 256 KiB), so no fit_batch call allocates,
+// frees or synchronises, and a graph captured earlier keeps a valid pointer.
 hipError_t fit_scratch_init(FitScratch* s) {
   hipError_t e = hipMalloc(&s->counters, 256);
   if (e != hipSuccess) return e;
-
+  e = hipMalloc(&s->order, sizeof(int32_t) * static_cast<size_t>(kMaxRankB));
+  if (e != hipSuccess) return e;
+  s->cap = kMaxRankB;
   return hipMemset(s->counters, 0, 256);
 }
 
@@ -76,23 +82,8 @@ hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s
   FitLaunchFn fn = pick_fit(n_gauss, bkg, a.obj, s->block);
   if (!fn) return hipErrorNotSupported;
   a.cache_bins = s->cache_bins;
-  a.sorted = a.B <= kMaxRankB ? 1 : 0;
-  if (a.sorted && a.B > s->cap) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(st, &cs);
-    if (e != hipSuccess) return e;
-    if (cs != hipStreamCaptureStatusNone) return hipErrorStreamCaptureUnsupported;
-    if (s->order) {
-      e = hipStreamSynchronize(st);
-      if (e != hipSuccess) return e;
-      (void)hipFree(s->order);
-      s->order = nullptr;
-      s->cap = 0;
-    }
-    e = hipMalloc(&s->order, sizeof(int32_t) * static_cast<size_t>(a.B));
-    if (e != hipSuccess) return e;
-    s->cap = a.B;
-  }
+  // batches above kMaxRankB run in index order (no ranking pass)
+  a.sorted = (a.B <= kMaxRankB && a.B <= s->cap) ? 1 : 0;
   a.order = s->order;
   a.counters = s->counters;
   if (a.sorted) {

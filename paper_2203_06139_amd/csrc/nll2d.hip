@@ -24,7 +24,7 @@ __device__ __forceinline__ void chunk_2d(const Model2D& M, const double2* __rest
   double e = 0.0, r = 0.0, Dw = 0.0;
   if constexpr (RECUR) {
     const double q0 = -0.5 * fma(w0, w0, v * v);
-    const double a0 = fmin(fmax(fma(-dw, w0, -0.5 * dw * dw), -700.0), 700.0);
+    const double a0 = clamp_ratio_exponent<F32BIN>(fma(-dw, w0, -0.5 * dw * dw));
     e = F32BIN ? exp_hw32(q0) : exp_fast(q0);
     r = F32BIN ? exp_hw32(a0) : exp_fast(a0);
     Dw = M.Dw;

@@ -94,3 +94,41 @@ def test_bin_average_flag_is_validated_on_the_host(lib):
     assert lib.hf_model_nparams(ctypes.byref(m)) == -2
     m = hf.HfModel(hf.GAUSS_POLY, 1, 1, 2, 0.0, 1.0)  # flag must be 0 or 1
     assert lib.hf_model_nparams(ctypes.byref(m)) == -1
+
+
+def test_mlp_workspace_layout_fits_the_workspace(lib):
+    """The stored values' views lie inside the workspace, in carve order,
+    without overlap."""
+    import paper_2203_06139_amd as hf
+    offs = (ctypes.c_int64 * 12)()
+    assert lib.hf_mlp_workspace_layout(63, offs) == -1
+    assert lib.hf_mlp_workspace_layout(64, None) == -1
+    for B in (64, 192, 1024):
+        assert lib.hf_mlp_workspace_layout(B, offs) == 0
+        total = lib.hf_mlp_workspace_bytes(B)
+        ins = (hf.MLP_IN, hf.MLP_HIDDEN, hf.MLP_HIDDEN, hf.MLP_HIDDEN)
+        outs = (hf.MLP_HIDDEN, hf.MLP_HIDDEN, hf.MLP_HIDDEN, hf.MLP_OUT_PAD)
+        sizes = [B * ins[l] * 2 for l in range(4)] + [B * 512 * 4] * 3 + [B * 32 * 4] + \
+                [B * outs[l] * 2 for l in range(4)]
+        spans = sorted(zip(list(offs), sizes))
+        for (o, n), (o2, _) in zip(spans, spans[1:]):
+            assert o + n <= o2
+        assert all(o % 256 == 0 for o in offs)
+        assert spans[-1][0] + spans[-1][1] <= total
+
+
+def test_binding_rejects_host_tensors_before_any_launch():
+    """Counts that are not device tensors are refused by the binding before it
+    looks for a GPU, so a host pointer never reaches a kernel."""
+    import numpy as np
+    import torch
+    import paper_2203_06139_amd as hf
+    m = hf.Model(hf.GAUSS_POLY, 1, 1)
+    h = hf.Hist(torch.ones(64, dtype=torch.int32), (0.0, 1.0))
+    th = np.array([10.0, 0.5, 0.1, 1.0, 0.0])
+    for call in (lambda: hf.nll_eval(h, m, th), lambda: hf.nll_grad(h, m, th),
+                 lambda: hf.nll_fisher(h, m, th)):
+        with pytest.raises(ValueError, match="device tensor"):
+            call()
+    with pytest.raises(ValueError, match="device tensor"):
+        hf.fit_batch(torch.ones(64, dtype=torch.int32), [0, 64], [[0.0, 1.0]], m, th[None, :])

@@ -166,6 +166,76 @@ def test_fit_batch_repeatable_and_graph_replay(hf):
         x = torch.randn(1000, device="cuda").sum()  # unrelated eager work
         torch.cuda.synchronize()
         del x
+    # a larger uncaptured batch on the capturing stream's context must not
+    # move the scratch the graph holds: replays still give the eager result
+    big, bth0 = _subset(200, seed=12)
+    with torch.cuda.stream(s):
+        hf.fit_batch(to_dev_counts(big["counts"]), torch.as_tensor(big["offsets"]).cuda(),
+                     torch.as_tensor(big["ranges"]).cuda(), m, torch.as_tensor(bth0).cuda(),
+                     precision=1, polish_edm=1e-3)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        out.theta.zero_()
+        out.nll.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out.theta, ref[0]) and torch.equal(out.nll, ref[1])
+
+
+def test_calls_on_two_streams_use_separate_scratch(hf):
+    """Objective calls on two streams, each serialised on its own stream but
+    free to overlap with the other, give the single-stream results: every
+    stream has its own context, so the block partials and completion ticket
+    are never shared between overlapping launches."""
+    import torch
+    spec = datagen.model_spec(1, 2, 3, 50.0, 50.0)
+    th = [700.0, 30.0, 4.0, 400.0, 62.0, 6.0, 100.0, -20.0, 10.0, 5.0]
+    cases = [datagen.random_1d_case(spec, 2_000_003 + k, 0.0, 100.0, th, seed=40 + k)
+             for k in range(2)]
+    m = hf.Model.from_spec(spec)
+    hists = [hf.make_hist(c["counts"], (0.0, 100.0)) for c in cases]
+    thetas = [torch.as_tensor(c["theta_eval"], dtype=torch.float64, device="cuda")
+              for c in cases]
+    ref = []
+    for h, t in zip(hists, thetas):
+        n, g_, _ = hf.nll_grad(h, m, t)
+        ref.append((n.clone(), g_.clone()))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [[], []]
+    for rep in range(8):
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                outs[k].append(hf.nll_grad(hists[k], m, thetas[k])[:2])
+    torch.cuda.synchronize()
+    for k in range(2):
+        for n, g_ in outs[k]:
+            assert torch.equal(n, ref[k][0]) and torch.equal(g_, ref[k][1]), k
+
+
+def test_strided_and_mistyped_tensors_are_refused(hf):
+    """The kernels read plain pointers, so the binding refuses tensors whose
+    memory is not laid out as the call reads it."""
+    import torch
+    m = hf.Model(hf.GAUSS_POLY, 1, 1)
+    th = [10.0, 0.5, 0.1, 1.0, 0.0]
+    c2 = torch.ones(64, 64, dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError, match="contiguous"):
+        hf.nll_eval(hf.Hist(c2.t(), (0.0, 1.0), (0.0, 1.0)), hf.Model(hf.GAUSS2D),
+                    [1.0, 0.5, 0.5, 0.1, 0.1, 0.0, 1.0])
+    c = torch.ones(128, dtype=torch.int32, device="cuda")
+    w = torch.ones(256, dtype=torch.float32, device="cuda")[::2]
+    with pytest.raises(ValueError):
+        hf.nll_grad(hf.Hist(c, (0.0, 1.0), weights=w), m, th)
+    with pytest.raises(ValueError):
+        hf.nll_grad(hf.Hist(c, (0.0, 1.0), weights=torch.ones(128, device="cuda",
+                                                               dtype=torch.float64)), m, th)
+    with pytest.raises(ValueError):
+        hf.nll_grad(hf.Hist(c, (0.0, 1.0)), m, th,
+                    grad_out=torch.empty(5, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        hf.nll_grad(hf.Hist(c, (0.0, 1.0)), m, th, want_grad_w=True,
+                    grad_w_out=torch.empty(256, dtype=torch.float32, device="cuda")[::2])
 
 
 def test_launch_shape_does_not_change_results(hf, orc):

@@ -71,10 +71,44 @@ def test_nll_grad_1d_parity(hf, orc, case, obj, prec):
         w = (np.random.default_rng(nbins).uniform(0.5, 1.5, nbins).astype(np.float32)
              if weighted else None)
         ref = orc.nll_grad(orc_model(orc, spec), obj, counts, c["theta_eval"], r,
-                           weights=None if w is None else w.astype(np.float64))
-        nll, grad, _, st = gpu_eval(hf, spec, counts, c["theta_eval"], r, obj, prec, weights=w)
+                           weights=None if w is None else w.astype(np.float64), want_ell=True)
+        if weighted:
+            # the per-bin weight gradient (grad_w = seed * l_i) on uniform bins,
+            # with an upstream seed that also scales the parameter gradient
+            import torch
+            sd = torch.tensor([0.75], dtype=torch.float64, device="cuda")
+            nll, grad, gw, st = gpu_eval(hf, spec, counts, c["theta_eval"], r, obj, prec,
+                                         weights=w, seed=sd, want_grad_w=True)
+            assert_close(ref, nll, grad, TOL[prec], (nbins, weighted), seed=0.75)
+            mu = orc.model_eval(orc_model(orc, spec), c["theta_eval"], (nbins,), r)
+            check_grad_w_1d(gw, ref, mu, counts, 0.75, prec)
+        else:
+            nll, grad, _, st = gpu_eval(hf, spec, counts, c["theta_eval"], r, obj, prec,
+                                        weights=w)
+            assert_close(ref, nll, grad, TOL[prec], (nbins, weighted))
         assert st == ref.status
-        assert_close(ref, nll, grad, TOL[prec], (nbins, weighted))
+
+
+def test_fp32_bins_gaussian_only_far_tails(hf, orc):
+    """FP32-per-bin with a Gaussian-only model over a range many widths wide:
+    in the tails the FP32 exps underflow to 0 (the model is below 1e-38
+    there), every tail bin is empty, and the result must still match the
+    FP64 oracle within the FP32-per-bin tolerance (Poisson, Neyman) with no
+    status bit set."""
+    spec = datagen.model_spec(1, 1, -1, 0.0, 1.0)
+    r = (0.0, 100.0)
+    th = np.array([5e3, 50.0, 1.5])
+    for nbins in (4099, 100_003):
+        c = datagen.random_1d_case(spec, nbins, r[0], r[1], th, seed=77 + nbins)
+        counts = c["counts"]
+        x = r[0] + (np.arange(nbins) + 0.5) * (r[1] - r[0]) / nbins
+        counts[np.abs(x - th[1]) > 13 * th[2]] = 0
+        for obj in (0, 2):
+            ref = orc.nll_grad(orc_model(orc, spec), obj, counts, c["theta_eval"], r)
+            nll, grad, _, st = gpu_eval(hf, spec, counts, c["theta_eval"], r, obj, 1)
+            assert st == 0 and ref.status == 0
+            assert np.isfinite(nll) and np.all(np.isfinite(grad))
+            assert_close(ref, nll, grad, TOL[1], (nbins, obj))
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -158,6 +192,20 @@ def check_grad_w(orc, gw, ref, th, counts, r, seed, prec):
     ny, nx = counts.shape
     mu = orc.model_eval(orc.Model(3), th, (ny, nx), r).reshape(-1)
     n = counts.reshape(-1).astype(np.float64)
+    expect = seed * ref.ell
+    if prec == 0:
+        tol = 4e-7 * np.abs(expect) + 1e-14 * abs(seed) * (np.abs(mu) + n)
+    else:
+        tol = 4e-6 * np.abs(expect) + 2e-6 * abs(seed) * (np.abs(mu - n) + 1e-3 * n)
+    err = np.abs(gw.reshape(-1).astype(np.float64) - expect)
+    assert np.all(err <= tol + 1e-30), float(np.max(err / (tol + 1e-30)))
+
+
+def check_grad_w_1d(gw, ref, mu, counts, seed, prec):
+    """1D uniform bins: grad_w_i = seed * l_i in FP32, with the same bound as
+    the 2D check (the FP32 rounding of the output plus a few ulps of the
+    cancelling operands of l)."""
+    n = np.asarray(counts, dtype=np.float64).reshape(-1)
     expect = seed * ref.ell
     if prec == 0:
         tol = 4e-7 * np.abs(expect) + 1e-14 * abs(seed) * (np.abs(mu) + n)
