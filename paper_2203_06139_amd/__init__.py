@@ -90,7 +90,9 @@ class HistfitError(RuntimeError):
 
 _lib = None
 _ctx = {}      # (device, stream handle) -> hf_ctx
+_pool = {}     # device -> contexts created ahead, not yet given to a stream
 _tuning = {}   # device -> (wg_per_cu, cache_bins, block_size) set by fit_set_tuning
+POOL_SIZE = 4  # spare contexts kept for streams first seen during graph capture
 
 
 def load():
@@ -152,32 +154,55 @@ def load():
     return L
 
 
-def context(device: int | None = None, stream=None):
-    """The library context of (device, stream): created on first use and kept
-    for the process.  A context's scratch (block partials, completion ticket,
-    fit queue) may only be used by calls that do not overlap, so every stream
-    gets its own: calls serialised on one stream share a context, and calls
-    on different streams (a graph captured on a side stream and eager work on
-    the default stream included) never do.  `stream` defaults to the
-    device's current torch stream."""
+def _new_context(dev):
     import torch
     L = load()
+    h = ctypes.c_void_p()
+    with torch.cuda.device(dev):
+        rc = L.hf_ctx_create(ctypes.byref(h), dev)
+    if rc != 0:
+        raise HistfitError("hf_ctx_create(%d) failed: %d" % (dev, rc))
+    if dev in _tuning:
+        _check(L.hf_fit_set_tuning(h, *_tuning[dev]), h)
+    return h
+
+
+def context(device: int | None = None, stream=None):
+    """The library context of (device, stream), kept for the process.  A
+    context's scratch (block partials, completion ticket, fit queue) may only
+    be used by calls that do not overlap, so every stream gets its own:
+    calls serialised on one stream share a context, and calls on different
+    streams (a graph captured on a side stream and eager work on the default
+    stream included) never do.  Creating a context allocates device memory,
+    which a stream being captured into a graph must not do, so calls outside
+    capture keep POOL_SIZE spare contexts ready, and a stream first seen
+    during capture takes one of them.  `stream` defaults to the device's
+    current torch stream."""
+    import torch
+    load()
     if not torch.cuda.is_available():
         raise HistfitError("no GPU visible: the HIP library has no CPU path")
     dev = torch.cuda.current_device() if device is None else int(device)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
     key = (dev, int(stream))
-    if key not in _ctx:
-        h = ctypes.c_void_p()
-        with torch.cuda.device(dev):
-            rc = L.hf_ctx_create(ctypes.byref(h), dev)
-        if rc != 0:
-            raise HistfitError("hf_ctx_create(%d) failed: %d" % (dev, rc))
-        if dev in _tuning:
-            _check(L.hf_fit_set_tuning(h, *_tuning[dev]), h)
+    h = _ctx.get(key)
+    pool = _pool.setdefault(dev, [])
+    if h is not None and len(pool) >= POOL_SIZE:
+        return h
+    capturing = torch.cuda.is_current_stream_capturing()
+    if h is None:
+        if not pool and capturing:
+            raise HistfitError("more than %d streams first used during graph capture on device "
+                               "%d (or the device's first call is captured); make one call on "
+                               "the stream outside capture first: contexts allocate device "
+                               "memory" % (POOL_SIZE, dev))
+        h = pool.pop(0) if pool else _new_context(dev)
         _ctx[key] = h
-    return _ctx[key]
+    if not capturing:
+        while len(pool) < POOL_SIZE:
+            pool.append(_new_context(dev))
+    return h
 
 
 def _check(rc, ctx):
@@ -551,8 +576,9 @@ def fit_set_tuning(wg_per_cu: int, cache_bins: int, block_size: int = 256, devic
     ctx = context(dev)
     _check(load().hf_fit_set_tuning(ctx, *shape), ctx)
     _tuning[dev] = shape
-    for (d, _), h in _ctx.items():
-        if d == dev and h is not ctx:
+    others = [h for (d, _), h in _ctx.items() if d == dev] + _pool.get(dev, [])
+    for h in others:
+        if h is not ctx:
             _check(load().hf_fit_set_tuning(h, *shape), h)
 
 

@@ -13,6 +13,7 @@
 #include <string>
 
 #include "../../include/histfit.h"
+#include "finish.hpp"
 #include "fisher_kernels.hpp"
 #include "fit_kernels.hpp"
 #include "gradmap.hpp"
@@ -49,8 +50,9 @@ constexpr int kMaxGrid = 8192;
 struct hf_ctx {
   int device = 0;
   int num_cu = 0;
+  int max_grid = kMaxGrid;  // blocks whose partials the scratch holds
   int blocks_per_cu = 0;  // 0: as many as the kernel's occupancy allows
-  std::map<hf::LaunchFn, int> occupancy;
+  std::map<hf::LaunchFn, std::pair<int, int>> occupancy;  // (blocks per CU, threads per block)
   std::map<hf::FisherFn, int> fisher_occupancy;
   std::string err;
   double* part = nullptr;
@@ -155,15 +157,16 @@ hf::LaunchFn pick_1d(int ng, int bkg, int obj, bool grad, bool f32) {
   }
 }
 
-// Grid for a grid-stride pass over nb bins in chunks of `chunk` bins: no more
-// blocks than can be resident at once (occupancy per CU x CUs), so the grid
-// runs in a single round, and the chunks split as evenly as that allows
-// (every thread gets ceil or floor of the same count).
-int objective_grid(const hf_ctx* c, int64_t nb, int chunk, int per_cu) {
+// Grid for a grid-stride pass over nb bins in chunks of `chunk` bins with
+// `block` threads per block: no more blocks than can be resident at once
+// (occupancy per CU x CUs), so the grid runs in a single round, and the
+// chunks split as evenly as that allows (every thread gets ceil or floor of
+// the same count).
+int objective_grid(const hf_ctx* c, int64_t nb, int chunk, int per_cu, int block = hf::kBlock) {
   const int64_t chunks = (nb + chunk - 1) / chunk;
-  const int64_t per_block = hf::kBlock;
+  const int64_t per_block = block;
   int64_t gmax = static_cast<int64_t>(c->num_cu) * per_cu;
-  if (gmax > kMaxGrid) gmax = kMaxGrid;
+  if (gmax > c->max_grid) gmax = c->max_grid;
   if (gmax < 1) gmax = 1;
   int64_t need = (chunks + per_block - 1) / per_block;
   if (need <= gmax) return static_cast<int>(need < 1 ? 1 : need);
@@ -276,29 +279,41 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
   a.t_scale = m->t_scale;
   a.part = c->part;
   a.part_flags = c->part_flags;
-  a.ticket = c->ticket;
   a.log_lut = c->log_lut;
   a.x_edges = h->x_edges;
   auto it = c->occupancy.find(fn);
   if (it == c->occupancy.end()) {
-    int occ = 0;
-    hipError_t e = fn(a, 0, stream, &occ);
+    int occ = 0, block = 0;
+    hipError_t e = fn(a, 0, stream, &occ, &block);
     if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
-    it = c->occupancy.emplace(fn, occ < 1 ? 1 : occ).first;
+    it = c->occupancy.emplace(fn, std::make_pair(occ < 1 ? 1 : occ, block)).first;
   }
   // The 2D kernel runs one block per CU even where its registers would allow
   // two: measured on the 2048^2 workload, 41.0 us at one block per CU and
   // 52.0 us at two.
-  const int occ = two_d ? 1 : it->second;
+  const int occ = two_d ? 1 : it->second.first;
+  const int block = it->second.second;
   const int per_cu = c->blocks_per_cu > 0 ? c->blocks_per_cu : occ;
   // 2D work items are 16-bin pieces of one row (a row's tail is a short piece)
   const int64_t items_bins =
       two_d ? ((a.nx + hf::kChunk2D - 1) / hf::kChunk2D) * hf::kChunk2D * a.ny : a.nx;
   const int chunk = two_d ? hf::kChunk2D
                           : (avg ? hf::kAvgChunk : (edges ? 1 : hf::chunk_bins(m->n_gauss)));
-  const int grid = objective_grid(c, items_bins, chunk, per_cu);
-  hipError_t e = fn(a, grid, stream, nullptr);
+  const int grid = objective_grid(c, items_bins, chunk, per_cu, block);
+  hipError_t e = fn(a, grid, stream, nullptr, nullptr);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  hf::FinishArgs f{};
+  f.part = c->part;
+  f.part_flags = c->part_flags;
+  f.G = grid;
+  f.NV = grad ? a.P + 1 : 1;
+  f.seed = seed;
+  f.nll_out = nll_out;
+  f.grad_out = grad ? grad_out : nullptr;
+  f.status_out = status_out;
+  f.free_mask = free_mask;
+  e = hf::launch_finish(f, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "finishing kernel launch");
   return HF_OK;
 }
 
@@ -417,11 +432,21 @@ HF_EXPORT int nll_unbinned(hf_ctx* c, const double* events, const float* weights
   a.t_scale = m->t_scale;
   a.part = c->part;
   a.part_flags = c->part_flags;
-  a.ticket = c->ticket;
   a.log_lut = c->log_lut;
   const bool vec = aligned16(events) && (reinterpret_cast<uintptr_t>(weights) & 7u) == 0;
-  hipError_t e = fn(a, vec, c->num_cu, kMaxGrid, reinterpret_cast<hipStream_t>(stream));
+  int grid = 0;
+  hipError_t e = fn(a, vec, c->num_cu, kMaxGrid, reinterpret_cast<hipStream_t>(stream), &grid);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  hf::FinishArgs f{};
+  f.part = c->part;
+  f.part_flags = c->part_flags;
+  f.G = grid;
+  f.NV = grad_out ? a.P + 1 : 1;
+  f.nll_out = nll_out;
+  f.grad_out = grad_out;
+  f.status_out = status_out;
+  e = hf::launch_finish(f, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "finishing kernel launch");
   return HF_OK;
 }
 

@@ -228,28 +228,32 @@ __device__ __forceinline__ void store_relaxed(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide deterministic completion of a multi-value sum.  Every block
-// publishes its block totals to part[k * G + block]; the block that takes the
-// last ticket sums the G partials of each component in block order (strided
-// over its threads, then the fixed block_sum tree) and returns true with the
-// grand totals in tot/totf.  That block also re-arms the ticket to 0, so the
-// counter needs clearing only once, when it is allocated.
+// Grid-wide deterministic completion of a multi-value sum in one kernel
+// (used where the outputs are not the objective's: the expected Hessian and
+// the gradient map's shared sums).  Every block publishes its block totals
+// to part[k * G + block]; the block that takes the last ticket sums the G
+// partials of each component in block order (strided over its threads, then
+// the fixed block_sum tree) and returns true with the grand totals in
+// tot/totf.  That block also re-arms the ticket to 0, so the counter needs
+// clearing only once, when it is allocated.
 //
 // Ordering: the partials are written by lanes of wave 0 only (NV <= 64), and
 // the same wave issues an agent-scope release fence before lane 0 takes the
-// ticket, so one L2 write-back per block publishes them; only the last block
-// pays the acquire (L2 invalidate) before reading them.  A seq_cst fence in
-// every wave of every block costs an order of magnitude more on gfx950.
-template <int NV>
+// ticket; only the last block pays the acquire before reading them, and it
+// requests every partial it sums before the first one is used (one memory
+// round trip: a loaded value that is then added before the next load is
+// requested would make one round trip per block stride).
+template <int NV, int BLOCK = kBlock>
 __device__ __forceinline__ bool grid_sum(double (&v)[NV], int flags, double* __restrict__ part,
                                          int* __restrict__ part_flags, unsigned* ticket,
                                          double* tot, int* totf) {
   static_assert(NV <= 64, "partials must be published by one wave");
-  __shared__ double red[kWaves][NV];
-  __shared__ int redf[kWaves];
+  constexpr int WAVES = BLOCK / 64;
+  __shared__ double red[WAVES][NV];
+  __shared__ int redf[WAVES];
   __shared__ int is_last;
   const int G = gridDim.x;
-  block_sum<NV>(v, flags, tot, totf, red, redf);
+  block_sum<NV, WAVES>(v, flags, tot, totf, red, redf);
   if (threadIdx.x < 64) {
     if (threadIdx.x < NV) store_relaxed(&part[threadIdx.x * G + blockIdx.x], tot[threadIdx.x]);
     if (threadIdx.x == 0) store_relaxed(&part_flags[blockIdx.x], *totf);
@@ -266,14 +270,60 @@ __device__ __forceinline__ bool grid_sum(double (&v)[NV], int flags, double* __r
 #pragma unroll
   for (int k = 0; k < NV; ++k) a[k] = 0.0;
   int f = 0;
-  for (int b = threadIdx.x; b < G; b += kBlock) {
+  // U strides' partials are requested together (fewer for wide NV, whose
+  // values already fill many registers); indices past G are clamped into
+  // range and their values dropped
+  constexpr int U = NV <= 17 ? 4 : 1;
+  for (int b0 = 0; b0 < G; b0 += U * BLOCK) {
+    double x[U][NV];
+    int fl[U];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) a[k] += load_relaxed(&part[k * G + b]);
-    f |= load_relaxed(&part_flags[b]);
+    for (int q = 0; q < U; ++q) {
+      const int b = min(b0 + q * BLOCK + static_cast<int>(threadIdx.x), G - 1);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) x[q][k] = load_relaxed(&part[k * G + b]);
+      fl[q] = load_relaxed(&part_flags[b]);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const bool in = b0 + q * BLOCK + static_cast<int>(threadIdx.x) < G;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) a[k] += in ? x[q][k] : 0.0;
+      f |= in ? fl[q] : 0;
+    }
   }
-  block_sum<NV>(a, f, tot, totf, red, redf);
+  block_sum<NV, WAVES>(a, f, tot, totf, red, redf);
   if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
+}
+
+// First half of the two-kernel completion of the objective calls: every
+// block sums v over its threads (fixed tree) and publishes
+//   part[k * G + block] = total_k * fac[k] + (block 0 ? add[k] : 0)
+// and its status flags; fac and add are block-shared arrays of NV values or
+// null (1 and 0).  The finishing kernel (k_finish_objective) then sums the
+// G partials in block order.  Completion of the kernel makes the partials
+// visible to the next one on the stream, so no fence, ticket or atomic is
+// needed, and every partial is overwritten by every call.
+template <int NV, int BLOCK = kBlock>
+__device__ __forceinline__ void grid_publish(double (&v)[NV], int flags, const double* fac,
+                                             const double* add, double* __restrict__ part,
+                                             int* __restrict__ part_flags) {
+  static_assert(NV <= BLOCK, "one thread per published value");
+  constexpr int WAVES = BLOCK / 64;
+  __shared__ double red[WAVES][NV];
+  __shared__ int redf[WAVES];
+  __shared__ double tot[NV];
+  __shared__ int totf;
+  const int G = gridDim.x;
+  block_sum<NV, WAVES>(v, flags, tot, &totf, red, redf);
+  const int k = threadIdx.x;
+  if (k < NV) {
+    double x = fac ? tot[k] * fac[k] : tot[k];
+    if (add && blockIdx.x == 0) x += add[k];
+    part[k * G + blockIdx.x] = x;
+  }
+  if (k == 0) part_flags[blockIdx.x] = totf;
 }
 
 __device__ __forceinline__ bool all_finite(const double* __restrict__ th, int P) {

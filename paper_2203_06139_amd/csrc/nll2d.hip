@@ -121,8 +121,9 @@ __global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_2d(NllArgs a) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
-  const double gseed = a.seed ? a.seed[0] : 1.0;  // adjoint of L (seeds theta and w)
-  const double seed = a.grad_w_out ? gseed : 1.0;
+  // the upstream adjoint scales grad_w here; the finishing kernel applies it
+  // to the parameter gradient
+  const double seed = (a.grad_w_out && a.seed) ? a.seed[0] : 1.0;
   const bool finite = all_finite(a.theta, a.P);
   const int64_t nx = a.nx;
   const int64_t cpr = (nx + K - 1) / K;  // chunks per row
@@ -197,15 +198,15 @@ __global__ __launch_bounds__(kBlock, kMinWaves) void k_nll_2d(NllArgs a) {
     }
   }
 
-  __shared__ double tot[NV];
-  __shared__ int totf;
-  if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
-    write_outputs<NV>(a, M, tot, totf, finite, gseed);
+  __shared__ double fac[NV];
+  if (threadIdx.x < NV) fac[threadIdx.x] = M.final_factor(threadIdx.x);
+  grid_publish<NV>(acc, flags | (finite ? 0 : ST_NONFINITE), fac, nullptr, a.part,
+                   a.part_flags);
 }
 
 template <int OBJ, bool GRAD, bool F32BIN>
-hipError_t launch_2d(const NllArgs& a, int grid, hipStream_t s, int* occ) {
-  return launch_or_occupancy(k_nll_2d<OBJ, GRAD, F32BIN>, a, grid, s, occ);
+hipError_t launch_2d(const NllArgs& a, int grid, hipStream_t s, int* occ, int* block) {
+  return launch_or_occupancy<kBlock>(k_nll_2d<OBJ, GRAD, F32BIN>, a, grid, s, occ, block);
 }
 
 template <int OBJ>

@@ -34,10 +34,6 @@ namespace hf {
 // Bins per thread per step of the bin-average kernel.
 constexpr int kAvgChunk = 8;
 
-struct UnitFactors {
-  __device__ __forceinline__ double final_factor(int) const { return 1.0; }
-};
-
 // a.x0 holds the left edge of bin 0 (not its centre) for these kernels.
 // EDGES: the bins' edges come from a.x_edges (any widths), else from the
 // uniform grid.
@@ -63,8 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
-  const double gseed = a.seed ? a.seed[0] : 1.0;
-  const double seed = a.grad_w_out ? gseed : 1.0;
+  const double seed = (a.grad_w_out && a.seed) ? a.seed[0] : 1.0;  // for grad_w
   const bool finite = all_finite(a.theta, a.P);
   const int64_t nb = a.nx;
   const int64_t nch = (nb + kAvgChunk - 1) / kAvgChunk;
@@ -161,10 +156,9 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
       xa = xb;
     }
   }
-  __shared__ double tot[NV];
-  __shared__ int totf;
-  if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
-    write_outputs<NV>(a, UnitFactors{}, tot, totf, finite, gseed);
+  // exact partials: no final factors
+  grid_publish<NV>(acc, flags | (finite ? 0 : ST_NONFINITE), nullptr, nullptr, a.part,
+                   a.part_flags);
 }
 
 // Centre model on bins of any widths: mu at each bin's midpoint, with the
@@ -206,8 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_edges(NllArgs a) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
-  const double gseed = a.seed ? a.seed[0] : 1.0;
-  const double seed = a.grad_w_out ? gseed : 1.0;
+  const double seed = (a.grad_w_out && a.seed) ? a.seed[0] : 1.0;  // for grad_w
   const bool finite = all_finite(a.theta, a.P);
   const int64_t nb = a.nx;
   const int64_t nch = (nb + K - 1) / K;
@@ -282,15 +275,15 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_edges(NllArgs a) {
       if (in && a.grad_w_out) a.grad_w_out[i0 + k] = static_cast<float>(seed * l);
     }
   }
-  __shared__ double tot[NV];
-  __shared__ int totf;
-  if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
-    write_outputs<NV>(a, M, tot, totf, finite, gseed);
+  __shared__ double fac[NV];
+  if (threadIdx.x < NV) fac[threadIdx.x] = M.final_factor(threadIdx.x);
+  grid_publish<NV>(acc, flags | (finite ? 0 : ST_NONFINITE), fac, nullptr, a.part,
+                   a.part_flags);
 }
 
 template <int NG, int BKG, int OBJ, bool GRAD>
-hipError_t launch_1d_edges(const NllArgs& a, int grid, hipStream_t s, int* occ) {
-  return launch_or_occupancy(k_nll_1d_edges<NG, BKG, OBJ, GRAD>, a, grid, s, occ);
+hipError_t launch_1d_edges(const NllArgs& a, int grid, hipStream_t s, int* occ, int* block) {
+  return launch_or_occupancy<kBlock>(k_nll_1d_edges<NG, BKG, OBJ, GRAD>, a, grid, s, occ, block);
 }
 
 template <int NG, int BKG>
@@ -332,8 +325,9 @@ LaunchFn pick_edges_ng(int bkg, int obj, bool grad) {
 }
 
 template <int NG, int BKG, int OBJ, bool GRAD, bool EDGES>
-hipError_t launch_1d_avg(const NllArgs& a, int grid, hipStream_t s, int* occ) {
-  return launch_or_occupancy(k_nll_1d_avg<NG, BKG, OBJ, GRAD, EDGES>, a, grid, s, occ);
+hipError_t launch_1d_avg(const NllArgs& a, int grid, hipStream_t s, int* occ, int* block) {
+  return launch_or_occupancy<kBlock>(k_nll_1d_avg<NG, BKG, OBJ, GRAD, EDGES>, a, grid, s, occ,
+                                     block);
 }
 
 template <int NG, int BKG, bool EDGES>

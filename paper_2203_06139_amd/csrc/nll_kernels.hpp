@@ -34,14 +34,16 @@ struct NllArgs {
   double t_shift, t_scale;
   double* part;
   int32_t* part_flags;
-  unsigned* ticket;
   const double2* log_lut;  // kLogLut entries, see log_lut_entry
   const double* x_edges;   // 1D bins of any widths: nx + 1 ascending edges, or null
 };
 
 // Launches a kernel variant with `grid` blocks; grid <= 0 instead returns,
-// through *occ, how many blocks of that kernel fit on one CU at once.
-using LaunchFn = hipError_t (*)(const NllArgs&, int grid, hipStream_t, int* occ);
+// through *occ, how many blocks of that kernel fit on one CU at once, and
+// through *block its threads per block.  The main kernel only publishes
+// per-block partials (grid_publish); the caller launches the finishing
+// kernel (launch_finish) after it.
+using LaunchFn = hipError_t (*)(const NllArgs&, int grid, hipStream_t, int* occ, int* block);
 
 __device__ __forceinline__ void load_counts4(const NllArgs& a, int64_t i0, double (&n)[4]) {
   if (a.dtype == DT_U32) {
@@ -67,33 +69,6 @@ __device__ __forceinline__ double load_count1(const NllArgs& a, int64_t i) {
   return static_cast<const double*>(a.counts)[i];
 }
 
-// Final stage shared by both kernels: the last block writes the outputs.
-// A non-finite theta makes every output NaN (and sets ST_NONFINITE), whatever
-// the clamped per-bin arithmetic produced; a domain error makes L = +inf and
-// the gradient NaN (the objective is not differentiable there).
-// `finite` (theta all finite) and `seed` are read in the kernel's prologue,
-// with theta: after the grid reduction's acquire they would be dependent
-// memory round trips at the very end of the call.
-template <int NV, class M>
-__device__ __forceinline__ void write_outputs(const NllArgs& a, const M& model, const double* tot,
-                                              int totf, bool finite, double seed) {
-  const int k = threadIdx.x;
-  const double nan = __builtin_nan("");
-  const bool domain = (totf & ST_DOMAIN) != 0;
-  if (k == 0) {
-    a.nll_out[0] = !finite ? nan : (domain ? __builtin_inf() : tot[0]);
-    if (a.status_out) a.status_out[0] = totf | (finite ? 0 : ST_NONFINITE);
-  }
-  if (NV > 1 && k >= 1 && k < NV) {
-    const bool free = (a.free_mask == 0u) || ((a.free_mask >> (k - 1)) & 1u);
-    a.grad_out[k - 1] =
-        (!finite || domain) ? nan : (free ? tot[k] * model.final_factor(k) * seed : 0.0);
-  }
-}
-
-// Bins per thread per step of the grid-stride loop (a multiple of 4: one
-// 16-byte load per 4 u32 counts), and the occupancy the register allocator
-// must leave room for (waves per SIMD).
 // Bins per thread per step (K) and waves per SIMD (W) the 1D kernel is built
 // for.  Every bin of a chunk is interleaved with the others, so registers
 // grow with K.  Measured with every call reading its 1e7 bins from HBM:
@@ -107,10 +82,14 @@ __device__ __forceinline__ void write_outputs(const NllArgs& a, const M& model, 
 // So two waves for the Poisson objective with up to two Gaussians, one wave
 // otherwise (three or more Gaussians need well over 256 VGPRs at 16 bins).
 // K is a multiple of 4 (16-byte loads).
+// Threads per block (BLOCK): 64 x 4 SIMDs x W, so one block fills a CU at
+// the kernel's occupancy and the grid has one block per CU (half as many
+// partials to publish and sum as two 256-thread blocks).
 template <int NG, int OBJ>
 struct Chunking {
   static constexpr int K = 16;
   static constexpr int W = (NG <= 2 && OBJ == OBJ_POISSON) ? 2 : 1;
+  static constexpr int BLOCK = 256 * W;
   static_assert(K % 4 == 0, "chunk must be a multiple of 4 bins");
 };
 constexpr int chunk_bins(int) { return 16; }
@@ -208,14 +187,16 @@ __device__ __forceinline__ void stream_chunks(const NllArgs& a, const Model1D<NG
 }
 
 template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN>
-__global__ __launch_bounds__(kBlock, (Chunking<NG, OBJ>::W)) void k_nll_1d(NllArgs a) {
+__global__ __launch_bounds__((Chunking<NG, OBJ>::BLOCK), (Chunking<NG, OBJ>::W)) void k_nll_1d(
+    NllArgs a) {
   constexpr int K = Chunking<NG, OBJ>::K;
+  constexpr int BLOCK = Chunking<NG, OBJ>::BLOCK;
   using S = Shape1D<NG, BKG>;
   constexpr int NV = GRAD ? S::P + 1 : 1;
   const int64_t nb = a.nx;
   const int64_t nfull = nb / K;
-  const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * BLOCK;
   const bool spec = a.dtype == DT_U32 && !a.weights;
   // the first chunk's counts are requested before the log table, so the two
   // memory latencies overlap instead of adding up
@@ -236,8 +217,9 @@ __global__ __launch_bounds__(kBlock, (Chunking<NG, OBJ>::W)) void k_nll_1d(NllAr
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   int flags = 0;
-  const double gseed = a.seed ? a.seed[0] : 1.0;  // adjoint of L (seeds theta and w)
-  const double seed = a.grad_w_out ? gseed : 1.0;
+  // the upstream adjoint scales grad_w here; the finishing kernel applies it
+  // to the parameter gradient
+  const double seed = (a.grad_w_out && a.seed) ? a.seed[0] : 1.0;
   const bool finite = all_finite(a.theta, a.P);
 
   if (spec) {
@@ -270,22 +252,27 @@ __global__ __launch_bounds__(kBlock, (Chunking<NG, OBJ>::W)) void k_nll_1d(NllAr
     if (a.grad_w_out) a.grad_w_out[i] = static_cast<float>(seed * l[0]);
   }
 
-  __shared__ double tot[NV];
-  __shared__ int totf;
-  if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf))
-    write_outputs<NV>(a, M, tot, totf, finite, gseed);
+  __shared__ double fac[NV];
+  if (threadIdx.x < NV) fac[threadIdx.x] = M.final_factor(threadIdx.x);
+  grid_publish<NV, BLOCK>(acc, flags | (finite ? 0 : ST_NONFINITE), fac, nullptr, a.part,
+                          a.part_flags);
 }
 
-template <class K>
-hipError_t launch_or_occupancy(K kernel, const NllArgs& a, int grid, hipStream_t s, int* occ) {
-  if (grid <= 0) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kernel, kBlock, 0);
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, a);
+template <int BLOCK, class K>
+hipError_t launch_or_occupancy(K kernel, const NllArgs& a, int grid, hipStream_t s, int* occ,
+                               int* block) {
+  if (grid <= 0) {
+    *block = BLOCK;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kernel, BLOCK, 0);
+  }
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, s, a);
   return hipGetLastError();
 }
 
 template <int NG, int BKG, int OBJ, bool GRAD, bool F32BIN>
-hipError_t launch_1d(const NllArgs& a, int grid, hipStream_t s, int* occ) {
-  return launch_or_occupancy(k_nll_1d<NG, BKG, OBJ, GRAD, F32BIN>, a, grid, s, occ);
+hipError_t launch_1d(const NllArgs& a, int grid, hipStream_t s, int* occ, int* block) {
+  return launch_or_occupancy<Chunking<NG, OBJ>::BLOCK>(k_nll_1d<NG, BKG, OBJ, GRAD, F32BIN>, a,
+                                                       grid, s, occ, block);
 }
 
 template <int NG, int BKG, int OBJ>

@@ -40,25 +40,20 @@ struct UnbinnedArgs {
   double t_shift, t_scale;
   double* part;
   int32_t* part_flags;
-  unsigned* ticket;
   const double2* log_lut;
 };
 
+// Launches the main kernel and returns the grid it used through *grid_used
+// (the caller then launches the finishing kernel over that many partials).
 using UnbinnedFn = hipError_t (*)(const UnbinnedArgs&, bool vec, int num_cu, int max_grid,
-                                  hipStream_t);
+                                  hipStream_t, int* grid_used);
 
-// Event pairs per thread per step (16-byte loads of two positions), and
-// whether the next step's positions are requested while the current step is
-// computed.  Measured on 1e7 events (two Gaussians + cubic): 4 pairs with the
-// prefetch 65.6 us; without it 80.5 us (8 pairs 68.6 us, 2 pairs 86.4 us);
-// 2 pairs with it 77.3 us.
-#ifndef HF_UB_PAIRS
-#define HF_UB_PAIRS 4
-#endif
-#ifndef HF_UB_PREFETCH
-#define HF_UB_PREFETCH 1
-#endif
-constexpr int kUbPairs = HF_UB_PAIRS;
+// Event pairs per thread per step (16-byte loads of two positions); the next
+// step's positions are requested while the current step is computed.
+// Measured on 1e7 events (two Gaussians + cubic): 4 pairs with the prefetch
+// 65.6 us; without it 80.5 us (8 pairs 68.6 us, 2 pairs 86.4 us); 2 pairs
+// with it 77.3 us.
+constexpr int kUbPairs = 4;
 
 template <int U>
 __device__ __forceinline__ void load_pairs(const UnbinnedArgs& a, int64_t q0, int64_t stride,
@@ -208,20 +203,16 @@ __global__ __launch_bounds__(kBlock) void k_nll_unbinned(UnbinnedArgs a) {
     const int64_t step = kUbPairs * stride;
     double2 xn[kUbPairs];
     float2 wn[kUbPairs];
-    if (HF_UB_PREFETCH) load_pairs(a, tid, stride, npair, xn, wn);
+    load_pairs(a, tid, stride, npair, xn, wn);
     for (int64_t q0 = tid; q0 < npair; q0 += step) {
       double2 xv[kUbPairs];
       float2 wv[kUbPairs];
-      if (HF_UB_PREFETCH) {
 #pragma unroll
-        for (int u = 0; u < kUbPairs; ++u) {
-          xv[u] = xn[u];
-          wv[u] = wn[u];
-        }
-        if (q0 + step < npair) load_pairs(a, q0 + step, stride, npair, xn, wn);
-      } else {
-        load_pairs(a, q0, stride, npair, xv, wv);
+      for (int u = 0; u < kUbPairs; ++u) {
+        xv[u] = xn[u];
+        wv[u] = wn[u];
       }
+      if (q0 + step < npair) load_pairs(a, q0 + step, stride, npair, xn, wn);
 #pragma unroll
       for (int u = 0; u < kUbPairs; ++u) {
         event_term<NG, BKG, GRAD>(a, M, lut, xv[u].x, wv[u].x, acc, flags);
@@ -234,24 +225,17 @@ __global__ __launch_bounds__(kBlock) void k_nll_unbinned(UnbinnedArgs a) {
     for (int64_t e = tid; e < a.n; e += stride)
       event_term<NG, BKG, GRAD>(a, M, lut, a.x[e], a.w ? a.w[e] : 1.0f, acc, flags);
   }
-  __shared__ double tot[NV];
-  __shared__ int totf;
-  if (grid_sum<NV>(acc, flags, a.part, a.part_flags, a.ticket, tot, &totf)) {
-    const int k = threadIdx.x;
-    const double nan = __builtin_nan("");
-    const bool domain = (totf & ST_DOMAIN) != 0;
-    if (k == 0) {
-      a.nll_out[0] = !finite ? nan : (domain ? __builtin_inf() : lamd[0] - tot[0]);
-      if (a.status_out) a.status_out[0] = totf | (finite ? 0 : ST_NONFINITE);
-    }
-    if (GRAD && k >= 1 && k < NV)
-      a.grad_out[k - 1] = (!finite || domain) ? nan : lamd[k] - tot[k] * ff[k];
-  }
+  // L = Lambda - sum w ln lambda: every block publishes -(its sums) times
+  // the final factors, and block 0 adds Lambda and its derivatives
+  __shared__ double fac[NV];
+  if (threadIdx.x < NV) fac[threadIdx.x] = -ff[threadIdx.x];
+  grid_publish<NV>(acc, flags | (finite ? 0 : ST_NONFINITE), fac, lamd, a.part, a.part_flags);
 }
 
 // Blocks per CU that fit (queried once per variant) bound a single round.
 template <int NG, int BKG, bool GRAD, bool VEC>
-hipError_t launch_unbinned_v(const UnbinnedArgs& a, int num_cu, int max_grid, hipStream_t s) {
+hipError_t launch_unbinned_v(const UnbinnedArgs& a, int num_cu, int max_grid, hipStream_t s,
+                             int* grid_used) {
   static const int occ = [] {
     int o = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_nll_unbinned<NG, BKG, GRAD, VEC>, kBlock,
@@ -265,18 +249,19 @@ hipError_t launch_unbinned_v(const UnbinnedArgs& a, int num_cu, int max_grid, hi
   if (grid > need) grid = need;
   if (grid > max_grid) grid = max_grid;
   if (grid < 1) grid = 1;
+  *grid_used = static_cast<int>(grid);
   hipLaunchKernelGGL((k_nll_unbinned<NG, BKG, GRAD, VEC>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 template <int NG, int BKG>
 hipError_t launch_unbinned(const UnbinnedArgs& a, bool vec, int num_cu, int max_grid,
-                           hipStream_t s) {
+                           hipStream_t s, int* grid_used) {
   if (a.grad_out)
-    return vec ? launch_unbinned_v<NG, BKG, true, true>(a, num_cu, max_grid, s)
-               : launch_unbinned_v<NG, BKG, true, false>(a, num_cu, max_grid, s);
-  return vec ? launch_unbinned_v<NG, BKG, false, true>(a, num_cu, max_grid, s)
-             : launch_unbinned_v<NG, BKG, false, false>(a, num_cu, max_grid, s);
+    return vec ? launch_unbinned_v<NG, BKG, true, true>(a, num_cu, max_grid, s, grid_used)
+               : launch_unbinned_v<NG, BKG, true, false>(a, num_cu, max_grid, s, grid_used);
+  return vec ? launch_unbinned_v<NG, BKG, false, true>(a, num_cu, max_grid, s, grid_used)
+             : launch_unbinned_v<NG, BKG, false, false>(a, num_cu, max_grid, s, grid_used);
 }
 
 // bkg: the background code (polynomial degree -1..3, or BKG_EXP).

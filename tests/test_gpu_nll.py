@@ -274,3 +274,33 @@ def test_full_size_2048_squared(hf, orc, prec):
     assert_close(ref, nll, grad, TOL[prec])
     check_grad_w(orc, gw, ref, c["theta_eval"], c["counts"], r, 1.0, prec)
     del torch
+
+
+def test_capture_on_a_stream_never_used_before(hf):
+    """A graph captured on a stream the library has not seen (no warm-up call
+    on it) takes a spare context, since creating one would allocate during
+    capture; replays give the eager result, with eager calls in between."""
+    import torch
+    spec, th, r = CASES_1D[1]
+    c = datagen.random_1d_case(spec, 300_007, r[0], r[1], th, seed=71)
+    h = hf.make_hist(c["counts"], r)
+    m = hf.Model.from_spec(spec)
+    t = torch.as_tensor(c["theta_eval"], dtype=torch.float64, device="cuda")
+    n0, g0, _ = hf.nll_grad(h, m, t)
+    torch.cuda.synchronize()
+    nll = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty(10, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            hf.nll_grad(h, m, t, nll_out=nll, grad_out=grad)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        nll.zero_()
+        grad.zero_()
+        g.replay()
+        hf.nll_grad(h, m, t)  # eager work on the default stream between replays
+        torch.cuda.synchronize()
+        assert torch.equal(nll, n0) and torch.equal(grad, g0)
