@@ -145,7 +145,8 @@ typedef struct {
 int hf_ctx_create(hf_ctx** out, int device);
 void hf_ctx_destroy(hf_ctx* ctx);
 /* Message of the last failing call on ctx (empty string if none); valid
- * until the next call on ctx.  ctx may be NULL for hf_ctx_create errors.  */
+ * until the next call on ctx.  With ctx NULL: the message of the calling
+ * thread's last failing context-free call (nll_grad_noalloc), or "".      */
 const char* hf_last_error(const hf_ctx* ctx);
 
 /* Number of parameters P of a model, or HF_EINVAL / HF_EUNSUPPORTED.      */
@@ -181,6 +182,27 @@ int nll_grad(hf_ctx* ctx, const hf_hist* hist, const hf_model* model, int32_t ob
              int32_t precision, const double* theta, const double* seed, double* nll_out,
              double* grad_out, float* grad_w_out, uint32_t free_mask, int32_t* status_out,
              hf_stream_t stream);
+
+/* nll_grad without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same computation and outputs as nll_grad, with the
+ * reduction scratch in a file-scope device array of the library (296 KiB
+ * per GPU, held until the process ends: the block partials of up to 2048
+ * blocks x 17 values, their status flags and the log table).  No call
+ * allocates or frees device memory; the first call on a device (with that
+ * device current) looks up the array's address there and copies the log
+ * table into it.  The kernels run on the calling thread's current device.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or threads) race and give wrong results; calls
+ * serialised on one stream do not.  Each call overwrites every partial it
+ * reads, so nothing needs clearing between calls.  Returns HF_EINVAL for a
+ * model of more than 16 parameters (the partials the array holds per
+ * block), and the errors of nll_grad otherwise; hf_last_error(NULL) gives
+ * the message of this thread's last failing call.                          */
+int nll_grad_noalloc(const hf_hist* hist, const hf_model* model, int32_t objective,
+                     int32_t precision, const double* theta, const double* seed, double* nll_out,
+                     double* grad_out, float* grad_w_out, uint32_t free_mask,
+                     int32_t* status_out, hf_stream_t stream);
 
 /* Extended unbinned NLL and its reverse-mode gradient: the binned
  * objective's per-bin evaluation applied to single events at arbitrary

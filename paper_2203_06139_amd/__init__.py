@@ -119,6 +119,9 @@ def load():
     L.nll_grad.argtypes = [vp, ctypes.POINTER(HfHist), ctypes.POINTER(HfModel), i32, i32, vp, vp,
                            vp, vp, vp, u32, vp, vp]
     L.nll_grad.restype = ctypes.c_int
+    L.nll_grad_noalloc.argtypes = [ctypes.POINTER(HfHist), ctypes.POINTER(HfModel), i32, i32, vp,
+                                   vp, vp, vp, vp, u32, vp, vp]
+    L.nll_grad_noalloc.restype = ctypes.c_int
     L.fit_batch.argtypes = [vp, i32, vp, i32, vp, vp, ctypes.POINTER(HfModel), i32, i32, vp,
                             ctypes.POINTER(HfFitOpts), vp, vp, vp, vp, vp, vp]
     L.fit_batch.restype = ctypes.c_int

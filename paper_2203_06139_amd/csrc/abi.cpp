@@ -10,6 +10,7 @@
 #include <map>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 
 #include "../../include/histfit.h"
@@ -367,7 +368,14 @@ HF_EXPORT void hf_ctx_destroy(hf_ctx* c) {
   delete c;
 }
 
-HF_EXPORT const char* hf_last_error(const hf_ctx* c) { return c ? c->err.c_str() : ""; }
+namespace {
+// Message of the last failing context-free call on this thread.
+thread_local std::string g_noalloc_err;
+}  // namespace
+
+HF_EXPORT const char* hf_last_error(const hf_ctx* c) {
+  return c ? c->err.c_str() : g_noalloc_err.c_str();
+}
 
 HF_EXPORT int hf_model_nparams(const hf_model* m) {
   const int rc = check_model(nullptr, m, true);
@@ -388,6 +396,106 @@ HF_EXPORT int nll_grad(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t o
                        hf_stream_t stream) {
   return run_objective(c, h, m, obj, prec, theta, seed, nll_out, grad_out, grad_w_out, free_mask,
                        status_out, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+// ---------------------------------------------------------------------------
+// nll_grad without a context: the scratch is a file-scope device array
+// ---------------------------------------------------------------------------
+namespace {
+
+// Partials of up to kStaticMaxGrid blocks x kStaticNV values (P <= 16), the
+// blocks' status flags and the log table, in one array per GPU:
+//   [0, 2 kLogLut)                      log table (kLogLut double2)
+//   [2 kLogLut, + kStaticNV kStaticMaxGrid)  block partials
+//   [..., + kStaticMaxGrid / 2)         int32 flags, one per block
+constexpr int kStaticMaxGrid = 2048;
+constexpr int kStaticNV = 17;
+constexpr size_t kScratchLut = 2 * static_cast<size_t>(hf::kLogLut);
+constexpr size_t kScratchPart = static_cast<size_t>(kStaticNV) * kStaticMaxGrid;
+constexpr size_t kScratchDoubles = kScratchLut + kScratchPart + kStaticMaxGrid / 2;
+static_assert(kStaticMaxGrid % 2 == 0, "flags fill whole doubles");
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+hf_ctx* g_static_ctx[kMaxDevices] = {};
+
+// The calling thread's current device's scratch, set up on first use: the
+// array's device address (each GPU holds its own copy of `scratch`), the
+// log table copied into it, the CU count.  Nothing is allocated on the
+// device; the host-side record is created once per device and kept.
+int static_context(hf_ctx** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    g_noalloc_err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return HF_EHIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_noalloc_err = "device index out of range";
+    return HF_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ctx[dev]) {
+    double* base = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&base), HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !base) {
+      g_noalloc_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return HF_EHIP;
+    }
+    int num_cu = 0;
+    e = hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || num_cu < 1) {
+      g_noalloc_err = "hipDeviceGetAttribute(multiprocessor count) failed";
+      return HF_EHIP;
+    }
+    double2 lut[hf::kLogLut];
+    for (int j = 0; j < hf::kLogLut; ++j) hf::log_lut_entry(j, &lut[j].x, &lut[j].y);
+    e = hipMemcpy(base, lut, sizeof lut, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      g_noalloc_err = std::string("log table copy: ") + hipGetErrorString(e);
+      return HF_EHIP;
+    }
+    hf_ctx* c = new hf_ctx();
+    c->device = dev;
+    c->num_cu = num_cu;
+    c->max_grid = kStaticMaxGrid;
+    c->log_lut = reinterpret_cast<double2*>(base);
+    c->part = base + kScratchLut;
+    c->part_flags = reinterpret_cast<int32_t*>(base + kScratchLut + kScratchPart);
+    g_static_ctx[dev] = c;
+  }
+  *out = g_static_ctx[dev];
+  return HF_OK;
+}
+
+}  // namespace
+
+HF_EXPORT int nll_grad_noalloc(const hf_hist* h, const hf_model* m, int32_t obj, int32_t prec,
+                               const double* theta, const double* seed, double* nll_out,
+                               double* grad_out, float* grad_w_out, uint32_t free_mask,
+                               int32_t* status_out, hf_stream_t stream) {
+  g_noalloc_err.clear();
+  if (!h || !m || !theta || !nll_out || !grad_out) {
+    g_noalloc_err = "nll_grad_noalloc: hist, model, theta, nll_out and grad_out must not be NULL";
+    return HF_EINVAL;
+  }
+  {
+    const int P = hf_model_nparams(m);
+    if (P > kStaticNV - 1) {
+      g_noalloc_err = "nll_grad_noalloc: the static scratch holds partials of at most 16 "
+                      "parameters";
+      return HF_EINVAL;
+    }
+  }
+  hf_ctx* c = nullptr;
+  int rc = static_context(&c);
+  if (rc) return rc;
+  rc = run_objective(c, h, m, obj, prec, theta, seed, nll_out, grad_out, grad_w_out, free_mask,
+                     status_out, reinterpret_cast<hipStream_t>(stream), true);
+  if (rc) g_noalloc_err = c->err;
+  return rc;
 }
 
 HF_EXPORT int nll_unbinned(hf_ctx* c, const double* events, const float* weights,
