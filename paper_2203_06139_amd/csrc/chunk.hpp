@@ -13,6 +13,11 @@
 // the FP32 exp takes it) so that 0 * r_0 stays 0.  Otherwise each bin takes
 // its own exp.
 //
+// A polynomial background is advanced by forward differences on a
+// recurrence chunk (degree additions per bin instead of forming t and
+// evaluating the polynomial); its rounding error grows by about one ulp of
+// the largest difference per bin, far below the objective's tolerance.
+//
 // Objective terms are branch-free (domain cases are only flagged), so the
 // compiler can interleave the K bins.
 #pragma once
@@ -101,6 +106,29 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
     const double a0 = fma(M.c[1], t0, M.c[0]);
     Eb = F32BIN ? exp_hw32(a0) : exp_fast(a0);
   }
+  // Polynomial background on a recurrence chunk by forward differences:
+  // b(t0 + k dt) = sum_j q_j k^j with q_j = dt^j sum_{i>=j} C(i,j) c_i t0^(i-j),
+  // and its differences at k = 0 advance by NB - 1 additions per bin.
+  constexpr int NBP = (BKG == BKG_EXP || S::NB <= 0) ? 1 : S::NB;
+  double fd[NBP];
+  if constexpr (RECUR && BKG != BKG_EXP && S::NB > 0) {
+    constexpr double C[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+    double q[NBP];
+    double dtp = 1.0;
+#pragma unroll
+    for (int j = 0; j < NBP; ++j) {
+      double sj = 0.0;
+#pragma unroll
+      for (int i = NBP - 1; i >= j; --i) sj = fma(sj, t0, C[i][j] * M.c[i]);
+      q[j] = sj * dtp;
+      dtp *= M.dt;
+    }
+    // differences of sum q_j k^j at k = 0 (degree <= 3)
+    fd[0] = q[0];
+    if constexpr (NBP > 1) fd[1] = q[1] + (NBP > 2 ? q[2] : 0.0) + (NBP > 3 ? q[3] : 0.0);
+    if constexpr (NBP > 2) fd[2] = 2.0 * q[2] + (NBP > 3 ? 6.0 * q[3] : 0.0);
+    if constexpr (NBP > 3) fd[3] = 6.0 * q[3];
+  }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     // ---- forward sweep ----
@@ -130,10 +158,16 @@ __device__ __forceinline__ void chunk_1d(const Model1D<NG, BKG>& M, const double
       }
       mu += E;
     } else if constexpr (S::NB > 0) {
-      double b = M.c[S::NB - 1];
+      if constexpr (RECUR) {
+        mu += fd[0];
 #pragma unroll
-      for (int j = S::NB - 2; j >= 0; --j) b = fma(b, t, M.c[j]);
-      mu += b;
+        for (int j = 0; j + 1 < NBP; ++j) fd[j] += fd[j + 1];
+      } else {
+        double b = M.c[S::NB - 1];
+#pragma unroll
+        for (int j = S::NB - 2; j >= 0; --j) b = fma(b, t, M.c[j]);
+        mu += b;
+      }
     }
     double l, ub;
     const bool dom = objective_t<OBJ, F32BIN>(n[k], mu, lut, l, ub);

@@ -20,7 +20,7 @@ struct FinishArgs {
   uint32_t free_mask;
 };
 
-// Launches the finishing kernel on `s` after the main kernel; G <= 8192,
+// Launches the finishing kernel on `s` after the main kernel; G >= 1,
 // 1 <= NV <= 17.
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 
