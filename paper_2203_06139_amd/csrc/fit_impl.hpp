@@ -274,6 +274,24 @@ __device__ bool fisher_start(FitShared<NG, BKG, BLK>& sm, int nf) {
   return ok;
 }
 
+// Sum over q < n of x[q] y[q] (or of x[q] when y is null), in order of q.
+// The first P entries are loaded up front, so the LDS reads overlap instead
+// of making one round trip per term.
+template <int P>
+__device__ __forceinline__ double dot_lds(const double* x, const double* y, int n) {
+  double v[P], w[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    v[q] = x[q];
+    w[q] = y ? y[q] : 1.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+    if (q < n) s = fma(v[q], w[q], s);
+  return s;
+}
+
 // f(u) and g_u = sigma * dL/dtheta at theta = theta0 + sigma * u.
 template <int NG, int BKG, int OBJ, int BLK>
 __device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
@@ -419,13 +437,13 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
     while (it < a.max_iter) {
       if (tid < nf) {
         double hg = 0.0;
-        for (int c = 0; c < nf; ++c) hg += sm.H[tid * P + c] * sm.g[c];
+        hg = dot_lds<P>(&sm.H[tid * P], sm.g, nf);
         sm.pv[tid] = -hg;
         sm.tmp[tid] = sm.g[tid] * hg;
       }
       __syncthreads();
       double edm = 0.0;
-      for (int q = 0; q < nf; ++q) edm += sm.tmp[q];
+      edm = dot_lds<P>(sm.tmp, nullptr, nf);
       edm *= 0.5;
       const double goal = fmax(a.edm_tol, 4.0 * DBL_EPSILON * fabs(f));
       if (f32 && a.polish_edm > 0.0 && edm < a.polish_edm) {
@@ -444,7 +462,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
         break;
       }
       double slope = 0.0;
-      for (int q = 0; q < nf; ++q) slope += sm.g[q] * sm.pv[q];
+      slope = dot_lds<P>(sm.g, sm.pv, nf);
       if (!(slope < 0.0)) {  // H lost positive definiteness: restart from I
         __syncthreads();
         for (int t = tid; t < P * P; t += BLK) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
@@ -452,7 +470,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
         first = true;
         __syncthreads();
         slope = 0.0;
-        for (int q = 0; q < nf; ++q) slope -= sm.g[q] * sm.g[q];
+        slope = -dot_lds<P>(sm.g, sm.g, nf);
       }
       double alpha = 1.0, fn = 0.0;
       bool accepted = false;
@@ -482,12 +500,9 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
         sm.yv[tid] = sm.gn[tid] - sm.g[tid];
       }
       __syncthreads();
-      double sy = 0.0, yy = 0.0, ss = 0.0;
-      for (int q = 0; q < nf; ++q) {
-        sy += sm.sv[q] * sm.yv[q];
-        yy += sm.yv[q] * sm.yv[q];
-        ss += sm.sv[q] * sm.sv[q];
-      }
+      const double sy = dot_lds<P>(sm.sv, sm.yv, nf);
+      const double yy = dot_lds<P>(sm.yv, sm.yv, nf);
+      const double ss = dot_lds<P>(sm.sv, sm.sv, nf);
       if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
         if (first) {
           const double gam = sy / yy;
@@ -497,12 +512,12 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
         }
         if (tid < nf) {
           double hy = 0.0;
-          for (int c = 0; c < nf; ++c) hy += sm.H[tid * P + c] * sm.yv[c];
+          hy = dot_lds<P>(&sm.H[tid * P], sm.yv, nf);
           sm.Hy[tid] = hy;
         }
         __syncthreads();
         double yHy = 0.0;
-        for (int q = 0; q < nf; ++q) yHy += sm.yv[q] * sm.Hy[q];
+        yHy = dot_lds<P>(sm.yv, sm.Hy, nf);
         const double rho = 1.0 / sy;
         const double cc = rho * rho * yHy + rho;
         for (int t = tid; t < nf * nf; t += BLK) {
