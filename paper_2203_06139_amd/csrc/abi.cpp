@@ -610,7 +610,6 @@ HF_EXPORT int hf_nll_fisher(hf_ctx* c, const hf_hist* h, const hf_model* m, int3
   a.t_scale = m->t_scale;
   a.part = c->part;
   a.part_flags = c->part_flags;
-  a.ticket = c->ticket;
   auto it = c->fisher_occupancy.find(fn);
   if (it == c->fisher_occupancy.end()) {
     int occ = 0;
@@ -626,9 +625,21 @@ HF_EXPORT int hf_nll_fisher(hf_ctx* c, const hf_hist* h, const hf_model* m, int3
       two_d ? ((a.nx + hf::kFisherChunk - 1) / hf::kFisherChunk) * hf::kFisherChunk * a.ny : a.nx;
   const int grid = objective_grid(c, items_bins, hf::kFisherChunk, per_cu);
   const int passes = hf::fisher_passes(a.P);
+  const int entries = a.P * (a.P + 1) / 2;
   for (int p = 0; p < passes; ++p) {
     hipError_t e = fn(a, p, grid, stream, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    hf::FinishSymArgs f{};
+    f.part = c->part;
+    f.part_flags = c->part_flags;
+    f.G = grid;
+    f.E0 = p * hf::kFisherQ;
+    f.NQ = std::min(hf::kFisherQ, entries - f.E0);
+    f.P = a.P;
+    f.out = fisher_out;
+    f.status_out = status_out;
+    e = hf::launch_finish_sym(f, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "finishing kernel launch");
   }
   return HF_OK;
 }

@@ -1,4 +1,5 @@
-// finish.hip -- the finishing kernel of the objective calls.
+// finish.hip -- the finishing kernels of the objective calls and of the
+// expected Hessian.
 //
 // The main kernel's blocks each publish their totals of the objective and
 // its gradient components (grid_publish); this one-block kernel sums them in
@@ -100,7 +101,61 @@ constexpr FinishFn kFinish[18] = {
     &launch_nv<10>, &launch_nv<11>, &launch_nv<12>, &launch_nv<13>, &launch_nv<14>,
     &launch_nv<15>, &launch_nv<16>, &launch_nv<17>};
 
+// One block per entry: the block's threads take the G partials in a fixed
+// assignment (thread t: blocks t, t + 256, ...), all requested before the
+// first add, and block_sum adds them up.
+__global__ __launch_bounds__(kFinishBlock) void k_finish_sym(FinishSymArgs a) {
+  constexpr int WAVES = kFinishBlock / 64;
+  constexpr int U = 8;
+  __shared__ double red[WAVES][1];
+  __shared__ int redf[WAVES];
+  __shared__ double tot[1];
+  __shared__ int totf;
+  const int q = blockIdx.x;
+  const int G = a.G;
+  const double* col = a.part + static_cast<int64_t>(q) * G;
+  double v[1] = {0.0};
+  int f = 0;
+  for (int b0 = 0; b0 < G; b0 += U * kFinishBlock) {
+    double x[U];
+    int fl[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = min(b0 + static_cast<int>(threadIdx.x) + u * kFinishBlock, G - 1);
+      x[u] = col[b];
+      fl[u] = a.part_flags[b];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = b0 + static_cast<int>(threadIdx.x) + u * kFinishBlock < G;
+      v[0] += in ? x[u] : 0.0;
+      f |= in ? fl[u] : 0;
+    }
+  }
+  block_sum<1, WAVES>(v, f, tot, &totf, red, redf);
+  if (threadIdx.x == 0) {
+    int r = 0, e = a.E0 + q;
+    while (e >= a.P - r) {
+      e -= a.P - r;
+      ++r;
+    }
+    const int c = r + e;
+    const bool finite = (totf & ST_NONFINITE) == 0;
+    const double val = finite ? tot[0] : __builtin_nan("");
+    a.out[r * a.P + c] = val;
+    a.out[c * a.P + r] = val;
+    if (q == 0 && a.E0 == 0 && a.status_out) a.status_out[0] = finite ? 0 : ST_NONFINITE;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_finish_sym(const FinishSymArgs& a, hipStream_t s) {
+  if (a.G < 1 || a.NQ < 1 || a.P < 1 || a.E0 < 0 || a.E0 + a.NQ > a.P * (a.P + 1) / 2 || !a.out)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finish_sym, dim3(a.NQ), dim3(kFinishBlock), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
   if (a.NV < 1 || a.NV > 17 || a.G < 1) return hipErrorInvalidValue;

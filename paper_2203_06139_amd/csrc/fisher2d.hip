@@ -175,10 +175,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_fisher_2d(FisherArgs a) {
     else
       fisher_piece_2d<NEY, false, K>(a, M, cp, cur, u0, v, du, sqD, acc);
   }
-  __shared__ double tot[NQ];
-  __shared__ int totf;
-  if (grid_sum<NQ>(acc, 0, a.part, a.part_flags, a.ticket, tot, &totf))
-    fisher_write<P, 0, NQ>(a, M, tot, finite);
+  fisher_publish<P, 0, NQ>(a, M, acc, finite);
 }
 
 template <bool NEY>

@@ -19,7 +19,8 @@
 // consecutive bins per thread, with the Gaussian and exponential recurrences
 // when they are valid), each thread keeping up to kFisherQ entries of the
 // upper triangle in registers; more entries (P > 10) take further passes
-// (launches), each over all bins.  grid_sum gives the fixed-order reduction.
+// (launches), each over all bins.  Every block publishes its totals
+// (grid_publish) and a finishing kernel adds them in block order.
 // On gfx950 the FP64 matrix cores have the same peak as the FP64 vector
 // FMAs, and a 16x16 tile would spend 256 products per bin on the
 // P(P+1)/2 = 55 (P = 10) that are needed, so the contraction stays on the
@@ -45,10 +46,9 @@ struct FisherArgs {
   double t_shift, t_scale;
   double* part;
   int32_t* part_flags;
-  unsigned* ticket;
 };
 
-// Upper-triangle entries per pass (one grid_sum publishes at most 64).
+// Upper-triangle entries per pass (one block publishes at most 64).
 #ifndef HF_FISHER_Q
 #define HF_FISHER_Q 64
 #endif
@@ -274,7 +274,10 @@ __device__ __forceinline__ void fisher_chunk_1d(const FisherArgs& a, const Model
   static_assert(K % 4 == 0, "chunk of whole 4-bin groups");
   FisherChunk1D<NG, BKG, RECUR> st(M, fma(static_cast<double>(i0), a.hx, a.x0));
   FisherRaw4 nxt = fisher_load4<NEY>(a, i0);
-#pragma unroll HF_FISHER_UNROLL
+  // chunks without the recurrences (narrow Gaussians) go one group at a
+  // time, so that their per-bin exps do not set the kernel's register count
+  constexpr int U = RECUR ? HF_FISHER_UNROLL : 1;
+#pragma unroll U
   for (int j = 0; j < K / 4; ++j) {
     const FisherRaw4 cur = nxt;
     if (j + 1 < K / 4) nxt = fisher_load4<NEY>(a, i0 + 4 * (j + 1));
@@ -283,6 +286,219 @@ __device__ __forceinline__ void fisher_chunk_1d(const FisherArgs& a, const Model
       double nk, wk;
       fisher_nw4<NEY>(a, cur, kk, i0 + 4 * j + kk, nk, wk);
       st.template bin<NEY, E0, NQ>(M, static_cast<double>(4 * j + kk), nk, wk, acc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Moment form of a recurrence chunk (every entry of F in one pass).
+//
+// Where the recurrences hold, every column of J is a group factor times a
+// polynomial in the bin's offset k within the chunk (z = z0 + k dz,
+// t = t0 + k dt):
+//   Gaussian g, factor e_g:  A: 1;  m: A z;  s: A z^2
+//   polynomial, factor 1:    t^j
+//   exponential, factor E:   E: 1;  t E: t
+// so the chunk's share of F_ab is a combination of the moments
+//   M_XY,m = sum_k c_k w_k f_X,k f_Y,k u^m,   m <= deg X + deg Y,
+// of the pair of groups (X, Y) the two columns belong to, in the distance
+// u = K-1-k from the chunk's last bin (z = z_e - u dz, t = t_e - u dt).
+// Per bin, the moments are kept in the binomial basis C(u, l) by nested
+// running sums (R_l += R_{l-1} from the top, then R_0 += weight: only adds,
+// no per-bin constants); once per chunk they are turned into powers of u,
+// u^m = sum_l l! S(m, l) C(u, l) with S the Stirling numbers of the second
+// kind, and expanded into the entries, column polynomial by column
+// polynomial.  34 running sums for two Gaussians and a cubic, against 55
+// entries per bin.
+// ---------------------------------------------------------------------------
+template <int NG, int BKG>
+struct FisherMoments {
+  using S = Shape1D<NG, BKG>;
+  static constexpr int P = S::P;
+  static constexpr bool EXPB = BKG == BKG_EXP;
+  static constexpr int NGRP = NG + (S::NB > 0 ? 1 : 0);
+  static constexpr int NPAIR = NGRP * (NGRP + 1) / 2;
+  static constexpr int deg(int X) { return X < NG ? 2 : (S::NB > 0 ? S::NB - 1 : 0); }
+  static constexpr int group(int j) { return j < 3 * NG ? j / 3 : NG; }
+  static constexpr int cdeg(int j) { return j < 3 * NG ? j % 3 : j - 3 * NG; }
+  static constexpr int first(int X) { return 3 * X; }  // first column of group X
+  static constexpr int pair(int X, int Y) { return X * NGRP - X * (X - 1) / 2 + (Y - X); }
+  static constexpr int entry(int a, int b) { return a * P - a * (a - 1) / 2 + (b - a); }
+  int off[NPAIR + 1];  // first moment of each pair
+  int px[NPAIR], py[NPAIR];
+  constexpr FisherMoments() : off(), px(), py() {
+    int p = 0, o = 0;
+    for (int X = 0; X < NGRP; ++X)
+      for (int Y = X; Y < NGRP; ++Y, ++p) {
+        px[p] = X;
+        py[p] = Y;
+        off[p] = o;
+        o += deg(X) + deg(Y) + 1;
+      }
+    off[NPAIR] = o;
+  }
+  static constexpr int count() {
+    int o = 0;
+    for (int X = 0; X < NGRP; ++X)
+      for (int Y = X; Y < NGRP; ++Y) o += deg(X) + deg(Y) + 1;
+    return o;
+  }
+  static constexpr int NMOM = count();
+};
+
+// A chunk of K consecutive bins starting at bin i0, by moments; every entry
+// of F (NQ = P(P+1)/2) is accumulated into acc.
+template <int NG, int BKG, bool NEY, int K, int NQ>
+__device__ __forceinline__ void fisher_chunk_moments(const FisherArgs& a, const Model1D<NG, BKG>& M,
+                                                     int64_t i0, double (&acc)[NQ]) {
+  using FM = FisherMoments<NG, BKG>;
+  using S = Shape1D<NG, BKG>;
+  constexpr int P = S::P;
+  constexpr int NGRP = FM::NGRP;
+  constexpr int NMOM = FM::NMOM;
+  constexpr FM fm{};
+  static_assert(NQ == P * (P + 1) / 2, "moment form takes every entry in one pass");
+  static_assert(K % 4 == 0 && K <= 16, "chunk of whole 4-bin groups");
+  FisherChunk1D<NG, BKG, true> st(M, fma(static_cast<double>(i0), a.hx, a.x0));
+  double mom[NMOM];
+#pragma unroll
+  for (int q = 0; q < NMOM; ++q) mom[q] = 0.0;
+  FisherRaw4 nxt = fisher_load4<NEY>(a, i0);
+#pragma unroll
+  for (int j = 0; j < K / 4; ++j) {
+    const FisherRaw4 cur = nxt;
+    if (j + 1 < K / 4) nxt = fisher_load4<NEY>(a, i0 + 4 * (j + 1));
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * j + kk;
+      double nk, wk;
+      fisher_nw4<NEY>(a, cur, kk, i0 + k, nk, wk);
+      double f[NGRP > 0 ? NGRP : 1];
+      double mu = 0.0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        f[g] = st.e[g];
+        mu = fma(M.A[g], st.e[g], mu);
+      }
+      double E = 0.0;
+      if constexpr (FM::EXPB) {
+        E = st.Eb;
+        st.Eb *= M.qE;
+        mu += E;
+      } else if constexpr (S::NB > 0) {
+        const double t = fma(static_cast<double>(k), M.dt, st.t0);
+        double b = M.c[S::NB - 1];
+#pragma unroll
+        for (int q = S::NB - 2; q >= 0; --q) b = fma(b, t, M.c[q]);
+        mu += b;
+      }
+      bool ok;
+      const double cw = fisher_weight<NEY>(nk, mu, wk, ok);
+      if constexpr (S::NB > 0) f[NG] = FM::EXPB ? (ok ? E : 0.0) : 1.0;
+      double cf[NGRP > 0 ? NGRP : 1];
+#pragma unroll
+      for (int X = 0; X < NGRP; ++X) cf[X] = cw * f[X];
+#pragma unroll
+      for (int p = 0; p < FM::NPAIR; ++p) {
+        const double w = (fm.py[p] == NG && !FM::EXPB) ? cf[fm.px[p]] : cf[fm.px[p]] * f[fm.py[p]];
+#pragma unroll
+        for (int l = fm.off[p + 1] - fm.off[p] - 1; l >= 1; --l)
+          mom[fm.off[p] + l] += mom[fm.off[p] + l - 1];
+        mom[fm.off[p]] += w;
+      }
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        st.e[g] *= st.r[g];
+        st.r[g] *= M.D[g];
+      }
+    }
+  }
+  // binomial basis -> powers of u (m! S(m, l), m <= 6)
+  constexpr double kStir[7][7] = {{1, 0, 0, 0, 0, 0, 0},        {0, 1, 0, 0, 0, 0, 0},
+                                  {0, 1, 2, 0, 0, 0, 0},        {0, 1, 6, 6, 0, 0, 0},
+                                  {0, 1, 14, 36, 24, 0, 0},     {0, 1, 30, 150, 240, 120, 0},
+                                  {0, 1, 62, 540, 1560, 1800, 720}};
+#pragma unroll
+  for (int p = 0; p < FM::NPAIR; ++p) {
+#pragma unroll
+    for (int m = fm.off[p + 1] - fm.off[p] - 1; m >= 2; --m) {
+      double v = mom[fm.off[p] + 1];
+#pragma unroll
+      for (int l = 2; l <= m; ++l) v = fma(kStir[m][l], mom[fm.off[p] + l], v);
+      mom[fm.off[p] + m] = v;
+    }
+  }
+  // column polynomials in u (about the chunk's last bin) and their scales
+  double cc[P][4];
+  double sc[P];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const double dz = -M.dz[g];
+    const double z0 = fma(static_cast<double>(K - 1), M.dz[g], st.z0[g]);
+    cc[3 * g][0] = 1.0;
+    sc[3 * g] = 1.0;
+    cc[3 * g + 1][0] = z0;
+    cc[3 * g + 1][1] = dz;
+    sc[3 * g + 1] = M.A[g];
+    cc[3 * g + 2][0] = z0 * z0;
+    cc[3 * g + 2][1] = 2.0 * z0 * dz;
+    cc[3 * g + 2][2] = dz * dz;
+    sc[3 * g + 2] = M.A[g];
+  }
+  if constexpr (S::NB > 0) {
+    // (t_e - u dt)^j by the binomial theorem
+    const double t0 = fma(static_cast<double>(K - 1), M.dt, st.t0), dt = -M.dt;
+    double tp[S::NB], dp[S::NB];
+    tp[0] = 1.0;
+    dp[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j < S::NB; ++j) {
+      tp[j] = tp[j - 1] * t0;
+      dp[j] = dp[j - 1] * dt;
+    }
+#pragma unroll
+    for (int j = 0; j < S::NB; ++j) {
+      double binom = 1.0;
+#pragma unroll
+      for (int l = 0; l <= j; ++l) {
+        cc[3 * NG + j][l] = binom * tp[j - l] * dp[l];
+        binom = binom * static_cast<double>(j - l) / static_cast<double>(l + 1);
+      }
+      sc[3 * NG + j] = 1.0;
+    }
+  }
+  // F_ab += sc_a sc_b sum_i cc_a,i W_b,i with W_b,i = sum_j cc_b,j M_XY,i+j
+#pragma unroll
+  for (int b = 0; b < P; ++b) {
+    const int Y = FM::group(b);
+    const int db = FM::cdeg(b);
+#pragma unroll
+    for (int X = 0; X < NGRP; ++X) {
+      if (X > Y) continue;
+      const int p = FM::pair(X, Y);
+      const int dX = FM::deg(X);
+      double W[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i > dX) continue;
+        double w = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          if (jj <= db) w = fma(cc[b][jj], mom[fm.off[p] + i + jj], w);
+        W[i] = w;
+      }
+      const int a0 = FM::first(X);
+      const int a1 = X < NG ? a0 + 3 : P;
+#pragma unroll
+      for (int aa = 0; aa < P; ++aa) {
+        if (aa < a0 || aa >= a1 || aa > b) continue;
+        double sv = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i <= FM::cdeg(aa)) sv = fma(cc[aa][i], W[i], sv);
+        const int q = FM::entry(aa, b);
+        acc[q] = fma(sc[aa] * sc[b], sv, acc[q]);
+      }
     }
   }
 }
@@ -297,15 +513,17 @@ __device__ __forceinline__ void fisher_bin_1d(const FisherArgs& a, const Model1D
   st.template bin<NEY, E0, NQ>(M, 0.0, nk, wk, acc);
 }
 
-// Writes the pass's entries of F (both triangles) from the block totals, each
-// times the columns' final factors and cfac; NaN when theta is not finite.
-// Called by every thread of the last block.
+// Publishes the block's totals of the pass's entries, each already times the
+// columns' final factors and cfac (grid_publish); the finishing kernel
+// (launch_finish_sym) adds them in block order and writes both triangles.
+// A theta that is not finite is passed on as ST_NONFINITE (NaN entries).
 template <int P, int E0, int NQ, class M>
-__device__ __forceinline__ void fisher_write(const FisherArgs& a, const M& model, const double* tot,
-                                             bool finite) {
+__device__ __forceinline__ void fisher_publish(const FisherArgs& a, const M& model,
+                                               double (&acc)[NQ], bool finite) {
   // the columns' factors go through LDS: indexing the model's arrays with a
   // thread-dependent column would place them in scratch memory
   __shared__ double ff[P];
+  __shared__ double fac[NQ];
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int j = 0; j < P; ++j) ff[j] = model.final_factor(1 + j);
@@ -319,12 +537,10 @@ __device__ __forceinline__ void fisher_write(const FisherArgs& a, const M& model
       e -= P - r;
       ++r;
     }
-    const int c = r + e;
-    const double v = finite ? tot[q] * ff[r] * ff[c] * a.cfac : __builtin_nan("");
-    a.fisher_out[r * P + c] = v;
-    a.fisher_out[c * P + r] = v;
+    fac[q] = ff[r] * ff[r + e] * a.cfac;
   }
-  if (E0 == 0 && q == 0 && a.status_out) a.status_out[0] = finite ? 0 : ST_NONFINITE;
+  // (block_sum's barriers inside grid_publish order these writes before use)
+  grid_publish<NQ>(acc, finite ? 0 : ST_NONFINITE, fac, nullptr, a.part, a.part_flags);
 }
 
 template <int NG, int BKG, bool NEY, int PASS>
@@ -345,17 +561,18 @@ __global__ __launch_bounds__(kBlock, 1) void k_fisher_1d(FisherArgs a) {
   const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   for (int64_t c = tid; c < nfull; c += stride) {
-    if (M.recur)
-      fisher_chunk_1d<NG, BKG, NEY, true, K, E0, NQ>(a, M, c * K, acc);
-    else
+    if (M.recur) {
+      if constexpr (NQ == TriIndex<P>::N)
+        fisher_chunk_moments<NG, BKG, NEY, K, NQ>(a, M, c * K, acc);
+      else
+        fisher_chunk_1d<NG, BKG, NEY, true, K, E0, NQ>(a, M, c * K, acc);
+    } else {
       fisher_chunk_1d<NG, BKG, NEY, false, K, E0, NQ>(a, M, c * K, acc);
+    }
   }
   const int64_t tail = nb - nfull * K;
   if (tid < tail) fisher_bin_1d<NG, BKG, NEY, E0, NQ>(a, M, nfull * K + tid, acc);
-  __shared__ double tot[NQ];
-  __shared__ int totf;
-  if (grid_sum<NQ>(acc, 0, a.part, a.part_flags, a.ticket, tot, &totf))
-    fisher_write<P, E0, NQ>(a, M, tot, finite);
+  fisher_publish<P, E0, NQ>(a, M, acc, finite);
 }
 
 template <int NG, int BKG, bool NEY, int PASS>

@@ -4,10 +4,11 @@
 // its reverse-mode gradient, over every bin of a 1D or 2D histogram
 // (paper sec. 4, Fig. 2a: the fit objective whose parameter gradient Clad
 // generates; sec. 2: reverse accumulation for a scalar function of many
-// parameters).  Schedule: a grid-stride loop over 4-bin chunks (one 16-byte
-// load of u32 counts per lane, so a wave reads 1 KiB contiguous), each thread
-// keeping P+1 FP64 accumulators in registers, then grid_sum() for the fixed
-// order reduction.  Bin centres are computed, never stored.
+// parameters).  Schedule: a grid-stride loop over 16-bin chunks (16-byte
+// loads of u32 counts), each thread keeping P+1 FP64 accumulators in
+// registers; every block publishes its totals (grid_publish) and the
+// finishing kernel (finish.hip) adds them in block order.  Bin centres are
+// computed, never stored.
 #pragma once
 
 #include "chunk.hpp"
