@@ -297,12 +297,13 @@ __device__ __forceinline__ bool grid_sum(double (&v)[NV], int flags, double* __r
   return true;
 }
 
-// First half of the two-kernel completion of the objective calls: every
-// block sums v over its threads (fixed tree) and publishes
+// First half of the two-kernel completion of the objective calls and the
+// expected Hessian: every block sums v over its threads (fixed tree) and
+// publishes
 //   part[k * G + block] = total_k * fac[k] + (block 0 ? add[k] : 0)
 // and its status flags; fac and add are block-shared arrays of NV values or
-// null (1 and 0).  The finishing kernel (k_finish_objective) then sums the
-// G partials in block order.  Completion of the kernel makes the partials
+// null (1 and 0).  A finishing kernel (finish.hip) then sums the G partials
+// of each value in block order.  Completion of the kernel makes the partials
 // visible to the next one on the stream, so no fence, ticket or atomic is
 // needed, and every partial is overwritten by every call.
 template <int NV, int BLOCK = kBlock>
