@@ -21,7 +21,10 @@
 // E_c = exp(b0 + b1 t_c) and S(u) = sinh(u)/u (d/db1 = E_c (t_c S + d S')).
 // A thread walks a chunk of consecutive bins edge to edge: each bin
 // evaluates erf and exp at its right edge and hands them to the next bin, so
-// a bin costs one erf and one exp per Gaussian.  The objective terms, the
+// a bin costs one erf and one exp per Gaussian.  On uniform bins narrower
+// than a sixteenth of every width, the Gaussians' averages and partials come
+// instead from a Hermite series about the bin centre, with exp at the
+// centres by the two-multiply recurrence (no erf; see k_nll_1d_avg).  The objective terms, the
 // reverse sweep (w ubar times the partials above) and the reduction are the
 // centre model's.  FP64 only.
 #pragma once
@@ -33,6 +36,33 @@ namespace hf {
 
 // Bins per thread per step of the bin-average kernel.
 constexpr int kAvgChunk = 8;
+
+// Terms of the bin-average Hermite series (see k_nll_1d_avg): at most 7.
+constexpr int kHermMax = 6;
+
+// sum_{k<=NH} He_2k(z) c_k, sum He_2k+1(z) c_k and sum_{k<=NH} He_2k+2(z) c_k
+// (He by He_{n+1} = z He_n - n He_{n-1}).
+template <int NH>
+__device__ __forceinline__ void herm_series(double z, const double (&c)[kHermMax + 1], double& sv,
+                                            double& tv, double& ux) {
+  double hm = 1.0, hc = z;
+  sv = c[0];
+  tv = c[0] * z;
+  ux = 0.0;
+#pragma unroll
+  for (int n = 1; n <= 2 * NH + 1; ++n) {
+    const double hn = fma(z, hc, -static_cast<double>(n) * hm);  // He_{n+1}
+    hm = hc;
+    hc = hn;
+    const int m = n + 1;
+    if (m % 2 == 0) {
+      if (m / 2 <= NH) sv = fma(c[m / 2], hn, sv);
+      ux = fma(c[m / 2 - 1], hn, ux);
+    } else if ((m - 1) / 2 <= NH) {
+      tv = fma(c[(m - 1) / 2], hn, tv);
+    }
+  }
+}
 
 // a.x0 holds the left edge of bin 0 (not its centre) for these kernels.
 // EDGES: the bins' edges come from a.x_edges (any widths), else from the
@@ -54,6 +84,36 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
   for (int g = 0; g < NG; ++g) sg[g] = a.theta[3 * g + 2];
   const double invh = 1.0 / a.hx;
   const double d = 0.5 * a.hx * M.ta;
+  // Uniform bins narrow against every width (16 |dz| <= 1, dz = h/s): the
+  // Gaussians' bin averages by the Hermite series about the bin centres,
+  // with exp at the centres by the two-multiply recurrence, instead of erf at
+  // the edges.  With phi(z) = exp(-z^2/2), phi^(n) = (-1)^n He_n phi, so over
+  // a bin [z_c - delta, z_c + delta] (delta = dz/2)
+  //   avg phi     = phi(z_c) sum_k He_2k(z_c)   c_k,
+  //   avg z phi   = phi(z_c) sum_k He_2k+1(z_c) c_k,
+  //   avg z^2 phi = phi(z_c) sum_k (He_2k+2 + He_2k)(z_c) c_k,
+  // c_k = delta^2k / (2k+1)!, and mu_g = A avg phi, dmu/dm = (A/s) avg z phi,
+  // dmu/ds = (A/s) avg z^2 phi.  The first omitted term is at most about
+  // (13 delta)^(2N+2)/(2N+3)! relative for |z_c| <= 9 (He_n(z) <= (|z| +
+  // sqrt n)^n) and phi < 3e-18 beyond; N = 1, 3 or 6 terms after the first
+  // keep it below 1e-19, 1e-19 and 3e-18 for delta up to 4.5e-6, 1.6e-3 and
+  // 1/32.
+  bool series = !EDGES && NG > 0;
+  double dmax = 0.0;
+  double dzs[G1], Dz[G1], cs[G1][kHermMax + 1];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    dzs[g] = a.hx * M.is[g];
+    series = series && 16.0 * fabs(dzs[g]) <= 1.0;
+    dmax = fmax(dmax, 0.5 * fabs(dzs[g]));
+    Dz[g] = exp_fast(-dzs[g] * dzs[g]);
+    const double d2 = 0.25 * dzs[g] * dzs[g];
+    cs[g][0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= kHermMax; ++k)
+      cs[g][k] = cs[g][k - 1] * d2 / static_cast<double>((2 * k) * (2 * k + 1));
+  }
+  const int nh = dmax <= 4.5e-6 ? 1 : (dmax <= 1.6e-3 ? 3 : kHermMax);
   if constexpr (OBJ == OBJ_POISSON) __syncthreads();
   double acc[NV];
 #pragma unroll
@@ -69,10 +129,20 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
     const int64_t i0 = c * kAvgChunk;
     const int len = static_cast<int>(nb - i0 < kAvgChunk ? nb - i0 : kAvgChunk);
     const double* __restrict__ E = EDGES ? a.x_edges : nullptr;
-    // left edge of the chunk's first bin
+    // erf path: z, erf and phi at the left edge of the current bin; series
+    // path: za = z at the chunk's first centre, ea = phi at the current
+    // centre and Ea its ratio to the next one
     double za[G1], Ea[G1], ea[G1];
     double xa = EDGES ? E[i0] : fma(static_cast<double>(i0), a.hx, a.x0);
-    {
+    if (series) {
+      const double xc = fma(static_cast<double>(i0) + 0.5, a.hx, a.x0);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        za[g] = (xc - M.m[g]) * M.is[g];  // z at the first centre
+        ea[g] = exp_fast(-0.5 * za[g] * za[g]);
+        Ea[g] = exp_fast(fmin(fmax(fma(-dzs[g], za[g], -0.5 * dzs[g] * dzs[g]), -700.0), 700.0));
+      }
+    } else {
       const double x = xa;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
@@ -98,22 +168,47 @@ __global__ __launch_bounds__(kBlock) void k_nll_1d_avg(NllArgs a) {
       const double ih = EDGES ? 1.0 / (xb - xa) : invh;
       double mu = 0.0;
       double J[P];
+      if (series) {
 #pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        const double zb = (xb - M.m[g]) * M.is[g];
-        const double Eb = erf(zb * kIr2);
-        const double eb = exp_fast(-0.5 * zb * zb);
-        const double ia = sg[g] * kRt * (Eb - Ea[g]) * ih;
-        const double mg = M.A[g] * ia;
-        mu += mg;
-        if constexpr (GRAD) {
-          J[3 * g] = ia;
-          J[3 * g + 1] = M.A[g] * (ea[g] - eb) * ih;
-          J[3 * g + 2] = fma(mg, M.is[g], M.A[g] * fma(za[g], ea[g], -zb * eb) * ih);
+        for (int g = 0; g < NG; ++g) {
+          const double z = fma(static_cast<double>(k), dzs[g], za[g]);  // centre
+          double sv, tv, ux;
+          if (nh == 1)
+            herm_series<1>(z, cs[g], sv, tv, ux);
+          else if (nh == 3)
+            herm_series<3>(z, cs[g], sv, tv, ux);
+          else
+            herm_series<kHermMax>(z, cs[g], sv, tv, ux);
+          const double es = ea[g] * sv;
+          const double mg = M.A[g] * es;
+          mu += mg;
+          if constexpr (GRAD) {
+            const double ae = M.A[g] * M.is[g] * ea[g];
+            J[3 * g] = es;
+            J[3 * g + 1] = ae * tv;
+            J[3 * g + 2] = ae * (sv + ux);
+          }
+          ea[g] *= Ea[g];  // phi at the next centre
+          Ea[g] *= Dz[g];
         }
-        za[g] = zb;
-        Ea[g] = Eb;
-        ea[g] = eb;
+      } else {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          const double zb = (xb - M.m[g]) * M.is[g];
+          const double Eb = erf(zb * kIr2);
+          const double eb = exp_fast(-0.5 * zb * zb);
+          const double ia = sg[g] * kRt * (Eb - Ea[g]) * ih;
+          const double mg = M.A[g] * ia;
+          mu += mg;
+          if constexpr (GRAD) {
+            J[3 * g] = ia;
+            J[3 * g + 1] = M.A[g] * (ea[g] - eb) * ih;
+            J[3 * g + 2] = fma(mg, M.is[g], M.A[g] * fma(za[g], ea[g], -zb * eb) * ih);
+          }
+          za[g] = zb;
+          Ea[g] = Eb;
+          ea[g] = eb;
+        }
       }
       if constexpr (BKG == BKG_EXP) {
         const double xc = EDGES ? 0.5 * (xa + xb) : fma(static_cast<double>(i) + 0.5, a.hx, a.x0);
