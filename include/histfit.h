@@ -365,6 +365,22 @@ int fit_batch(hf_ctx* ctx, int32_t B, const void* counts_concat, int32_t counts_
 int hf_fit_set_tuning(hf_ctx* ctx, int32_t wg_per_cu, int32_t cache_bins, int32_t block_size);
 int hf_fit_get_tuning(const hf_ctx* ctx, int32_t* wg_per_cu, int32_t* cache_bins,
                       int32_t* block_size);
+/* One wave per small histogram in fit_batch (a schedule knob like those
+ * of hf_fit_set_tuning): once the longest-first queue reaches histograms of
+ * at most wave_bins bins, every wave of a workgroup fits its own histogram,
+ * its state and (u32 counts) an LDS copy of the counts in a slot of its
+ * own, with wave-level reductions and no workgroup barriers; larger
+ * histograms keep a whole workgroup each.  0 (default) turns it off; it also
+ * stays off for batches above 65,536 histograms, which run unsorted.  At
+ * most hf_fit_max_wave_bins() for the model, objective and block size,
+ * checked by fit_batch (HF_EINVAL).  The results do not depend on it beyond
+ * summation order.  Host-only; HF_EINVAL for wave_bins < 0.
+ * hf_fit_get_wave_bins returns the setting (or HF_EINVAL for NULL).      */
+int hf_fit_set_wave_bins(hf_ctx* ctx, int32_t wave_bins);
+int hf_fit_get_wave_bins(const hf_ctx* ctx);
+int hf_fit_max_wave_bins(hf_ctx* ctx, const hf_model* model, int32_t objective,
+                         int32_t block_size);
+
 /* Largest cache_bins the fit kernel of this model and objective, with
  * workgroups of block_size threads, can hold in LDS next to its own state
  * (>= 0), or a negative hf_error.                                         */

@@ -92,6 +92,7 @@ _lib = None
 _ctx = {}      # (device, stream handle) -> hf_ctx
 _pool = {}     # device -> contexts created ahead, not yet given to a stream
 _tuning = {}   # device -> (wg_per_cu, cache_bins, block_size) set by fit_set_tuning
+_wave_bins = {}  # device -> wave_bins set by fit_set_wave_bins
 POOL_SIZE = 4  # spare contexts kept for streams first seen during graph capture
 
 
@@ -140,6 +141,9 @@ def load():
     L.hf_mlp_forward.argtypes = [vp, i32, vp, vp, vp, vp, i64, vp]
     L.hf_mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp, vp, i64, vp]
     L.hf_fit_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.hf_fit_set_wave_bins.argtypes = [vp, i32]
+    L.hf_fit_get_wave_bins.argtypes = [vp]
+    L.hf_fit_max_wave_bins.argtypes = [vp, ctypes.POINTER(HfModel), i32, i32]
     L.hf_fit_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]
     L.hf_fit_max_cache_bins.argtypes = [vp, ctypes.POINTER(HfModel), i32, i32]
@@ -151,7 +155,8 @@ def load():
                                ctypes.POINTER(HfModel), vp, vp, vp, vp, vp]
     for fn in (L.nll_unbinned, L.hf_gauss_grad_map, L.hf_nll_fisher, L.hf_fisher_covariance, L.hf_rebin_lognorm, L.hf_default_starts, L.hf_column_stats, L.hf_theta_to_target,
                L.hf_target_to_theta, L.hf_mlp_forward, L.hf_mlp_train_step, L.hf_fit_set_tuning,
-               L.hf_fit_get_tuning, L.hf_fit_max_cache_bins):
+               L.hf_fit_get_tuning, L.hf_fit_max_cache_bins, L.hf_fit_set_wave_bins,
+               L.hf_fit_get_wave_bins, L.hf_fit_max_wave_bins):
         fn.restype = ctypes.c_int
     _lib = L
     return L
@@ -167,6 +172,8 @@ def _new_context(dev):
         raise HistfitError("hf_ctx_create(%d) failed: %d" % (dev, rc))
     if dev in _tuning:
         _check(L.hf_fit_set_tuning(h, *_tuning[dev]), h)
+    if dev in _wave_bins:
+        _check(L.hf_fit_set_wave_bins(h, _wave_bins[dev]), h)
     return h
 
 
@@ -583,6 +590,31 @@ def fit_set_tuning(wg_per_cu: int, cache_bins: int, block_size: int = 256, devic
     for h in others:
         if h is not ctx:
             _check(load().hf_fit_set_tuning(h, *shape), h)
+
+
+def fit_set_wave_bins(wave_bins: int, device=None):
+    """One wave per histogram of at most wave_bins bins in fit_batch (see
+    hf_fit_set_wave_bins; 0 turns it off) on every context of the device."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    ctx = context(dev)
+    _check(load().hf_fit_set_wave_bins(ctx, int(wave_bins)), ctx)
+    _wave_bins[dev] = int(wave_bins)
+    others = [h for (d, _), h in _ctx.items() if d == dev] + _pool.get(dev, [])
+    for h in others:
+        if h is not ctx:
+            _check(load().hf_fit_set_wave_bins(h, int(wave_bins)), h)
+
+
+def fit_get_wave_bins(device=None) -> int:
+    return int(load().hf_fit_get_wave_bins(context(device)))
+
+
+def fit_max_wave_bins(model: Model, objective=POISSON, block_size: int = 256, device=None) -> int:
+    ctx = context(device)
+    rc = load().hf_fit_max_wave_bins(ctx, ctypes.byref(model.c()), objective, int(block_size))
+    _check(rc if rc < 0 else 0, ctx)
+    return rc
 
 
 def fit_get_tuning(device=None):

@@ -5,8 +5,10 @@ CU x the LDS count cache (in bins) x the FP32->FP64 polish threshold by
 timing fit_batch (HIP events) on a sample of the batch to be fitted (the
 whole batch when `sample` is at least its size), keeps the fastest
 configuration whose fits agree with the FP64 fit of the same sample
-(|dNLL| < 1e-6 where both converge), applies it to the device's contexts, and
-caches it as JSON keyed by (GPU arch, CU count, model, objective, precision).
+(|dNLL| < 1e-6 where both converge), then on that shape the size below which
+every wave fits a histogram of its own (wave_bins: off, 256 .. 2048 bins),
+applies the result to the device's contexts, and caches it as JSON keyed by
+(GPU arch, CU count, model, objective, precision).
 When no configuration agrees, the shape in place before the search is
 restored and RuntimeError is raised.  Cache file: $HF_AUTOTUNE_CACHE or
 ~/.cache/histfit/autotune.json.
@@ -19,12 +21,13 @@ import os
 
 import torch
 
-from . import (FP32_BIN, FP64, POISSON, Model, fit_batch, fit_get_tuning, fit_max_cache_bins,
-               fit_set_tuning)
+from . import (FP32_BIN, FP64, POISSON, Model, fit_batch, fit_get_tuning, fit_get_wave_bins,
+               fit_max_cache_bins, fit_max_wave_bins, fit_set_tuning, fit_set_wave_bins)
 
 BLOCKS = (256, 512)
 WG_PER_CU = (1, 2, 4, 8)
 POLISH = (1e-2, 1e-3, 1e-4)
+WAVE_BINS = (256, 512, 1024, 2048)
 
 
 def cache_path() -> str:
@@ -65,8 +68,11 @@ def tune_fit(counts, offsets, ranges, model: Model, theta0, objective=POISSON, p
         if k in known:
             c = known[k]
             fit_set_tuning(c["wg_per_cu"], c["cache_bins"], c.get("block_size", 256))
+            fit_set_wave_bins(c.get("wave_bins", 0))
             return c, []
     before = fit_get_tuning()
+    before_waves = fit_get_wave_bins()
+    fit_set_wave_bins(0)
     B = offsets.numel() - 1
     g = torch.Generator().manual_seed(seed)
     idx = torch.randperm(B, generator=g)[:min(sample, B)].sort().values
@@ -95,10 +101,30 @@ def tune_fit(counts, offsets, ranges, model: Model, theta0, objective=POISSON, p
     ok = [r for r in results if r["agree"]]
     if not ok:
         fit_set_tuning(*before)
+        fit_set_wave_bins(before_waves)
         raise RuntimeError("no launch shape reproduced the FP64 fits of the sample within 1e-6; "
                            "the previous shape %r is kept" % (before,))
-    best = min(ok, key=lambda r: r["ms"])
+    best = dict(min(ok, key=lambda r: r["ms"]), wave_bins=0)
     fit_set_tuning(best["wg_per_cu"], best["cache_bins"], best["block_size"])
+    # second stage, on the chosen shape: one wave per histogram below wave_bins
+    capw = fit_max_wave_bins(model, objective, best["block_size"])
+    run = lambda: fit_batch(fs.counts, fs.offsets, fs.ranges, model, th0, objective=objective,
+                            precision=precision, polish_edm=best["polish_edm"])
+    for wb in WAVE_BINS:
+        if wb > capw:
+            continue
+        fit_set_wave_bins(wb)
+        ms = _time(run)
+        out = run()
+        both = (out.status == 0) & (ref.status == 0)
+        agree = bool(((out.nll - ref.nll).abs()[both] < 1e-6).all().item())
+        r = dict(best, wave_bins=wb, ms=ms, agree=agree)
+        results.append(r)
+        if log:
+            log(r)
+        if agree and ms < best["ms"]:
+            best = r
+    fit_set_wave_bins(best["wave_bins"])
     if use_cache:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         known = {}

@@ -742,6 +742,12 @@ HF_EXPORT int fit_batch(hf_ctx* c, int32_t B, const void* counts, int32_t dtype,
       return fail(c, HF_EINVAL, "LDS cache of %d bins exceeds the %d this fit kernel can hold",
                   c->fit.cache_bins, cap);
   }
+  if (c->fit.wave_bins > 0) {
+    const int cap = hf::fit_max_wave_bins(m->n_gauss, bkg_code(m), obj, c->fit.block);
+    if (c->fit.wave_bins > cap)
+      return fail(c, HF_EINVAL, "wave_bins %d exceeds the %d this model's waves can hold in LDS",
+                  c->fit.wave_bins, cap);
+  }
   rc = use_device(c);
   if (rc) return rc;
 
@@ -917,6 +923,30 @@ HF_EXPORT int hf_fit_set_tuning(hf_ctx* c, int32_t wg_per_cu, int32_t cache_bins
   c->fit.cache_bins = cache_bins;
   c->fit.block = block_size;
   return HF_OK;
+}
+
+HF_EXPORT int hf_fit_set_wave_bins(hf_ctx* c, int32_t wave_bins) {
+  if (!c) return HF_EINVAL;
+  if (wave_bins < 0) return fail(c, HF_EINVAL, "wave_bins must be >= 0");
+  c->fit.wave_bins = wave_bins;
+  return HF_OK;
+}
+
+HF_EXPORT int hf_fit_get_wave_bins(const hf_ctx* c) {
+  return c ? c->fit.wave_bins : HF_EINVAL;
+}
+
+HF_EXPORT int hf_fit_max_wave_bins(hf_ctx* c, const hf_model* m, int32_t objective,
+                                   int32_t block_size) {
+  if (!c) return HF_EINVAL;
+  int rc = check_model(c, m);
+  if (rc) return rc;
+  if (m->kind == HF_GAUSS2D) return fail(c, HF_EUNSUPPORTED, "fit_batch takes 1D models only");
+  if (objective < HF_NEYMAN || objective > HF_POISSON) return fail(c, HF_EINVAL, "objective unknown");
+  rc = use_device(c);
+  if (rc) return rc;
+  if (block_size != 256 && block_size != 512) return fail(c, HF_EINVAL, "block_size must be 256 or 512");
+  return hf::fit_max_wave_bins(m->n_gauss, bkg_code(m), objective, block_size);
 }
 
 HF_EXPORT int hf_fit_get_tuning(const hf_ctx* c, int32_t* wg_per_cu, int32_t* cache_bins,

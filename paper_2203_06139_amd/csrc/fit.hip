@@ -78,10 +78,18 @@ int fit_max_cache_bins(int n_gauss, int bkg, int obj, int block) {
   return m > 0 ? m : 0;
 }
 
+int fit_max_wave_bins(int n_gauss, int bkg, int obj, int block) {
+  FitLaunchFn fn = pick_fit(n_gauss, bkg, obj, block);
+  int m = 0;
+  if (!fn || fn(FitArgs{}, -1, nullptr, &m) != hipSuccess) return 0;
+  return m > 0 ? m : 0;
+}
+
 hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s, hipStream_t st) {
   FitLaunchFn fn = pick_fit(n_gauss, bkg, a.obj, s->block);
   if (!fn) return hipErrorNotSupported;
   a.cache_bins = s->cache_bins;
+  a.wave_bins = s->wave_bins;
   // batches above kMaxRankB run in index order (no ranking pass)
   a.sorted = (a.B <= kMaxRankB && a.B <= s->cap) ? 1 : 0;
   a.order = s->order;

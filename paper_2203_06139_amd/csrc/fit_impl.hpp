@@ -83,13 +83,53 @@ struct CountsSrc {
   }
 };
 
+// The threads that run one fit: the workgroup (BLK = 256 or 512), or one
+// wave (BLK = 64) for the small histograms at the end of the longest-first
+// queue.  gtid is the thread's index in its group, gsync the group's
+// barrier (for a wave: LDS operations stay in program order, so a fence and
+// a code-motion barrier are enough), group_sum the group's fixed-order sum.
+template <int BLK>
+__device__ __forceinline__ int gtid() {
+  return BLK == 64 ? static_cast<int>(threadIdx.x & 63u) : static_cast<int>(threadIdx.x);
+}
+
+template <int BLK>
+__device__ __forceinline__ void gsync() {
+  if constexpr (BLK == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int NV, int BLK>
+__device__ __forceinline__ void group_sum(double (&v)[NV], int flags, double* tot, int* totf,
+                                          double (*red)[NV], int* redf) {
+  if constexpr (BLK == 64) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    const int f = (__ballot(flags & ST_DOMAIN) ? ST_DOMAIN : 0) |
+                  (__ballot(flags & ST_NONFINITE) ? ST_NONFINITE : 0);
+    if ((threadIdx.x & 63u) == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) tot[k] = v[k];
+      *totf = f;
+    }
+    gsync<64>();
+  } else {
+    block_sum<NV, BLK / 64>(v, flags, tot, totf, red, redf);
+  }
+}
+
 // Objective (and with GRAD its gradient) of one histogram at sm.th,
 // evaluated by the whole workgroup with the chunked sweep (chunk_1d).
 // Leaves f in sm.tot[0] (+inf on a domain error) and dL/dtheta_k in
 // sm.tot[1 + k].
 template <int NG, int BKG, int OBJ, bool F32BIN, bool GRAD, int BLK>
-__device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
-                        const CountsSrc& src, int64_t nb, double x0, double hx) {
+__device__ __forceinline__ void wg_eval(const FitArgs& a, FitShared<NG, BKG, BLK>& sm,
+    const double2* lut, const CountsSrc& src, int64_t nb, double x0, double hx) {
   constexpr int NV = GRAD ? FitShared<NG, BKG, BLK>::NV : 1;
   constexpr int K = kFitChunk;
   Model1D<NG, BKG> M;
@@ -101,7 +141,7 @@ __device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
   int flags = 0;
   const int64_t nch = nb / K;
   const double w[K] = {1.0, 1.0, 1.0, 1.0};
-  for (int64_t c = threadIdx.x; c < nch; c += BLK) {
+  for (int64_t c = gtid<BLK>(); c < nch; c += BLK) {
     const int64_t i0 = c * K;
     double n[K];
 #pragma unroll
@@ -113,18 +153,18 @@ __device__ void wg_eval(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
     else
       chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, false>(M, lut, xs, n, w, acc, flags, l);
   }
-  for (int64_t i = nch * K + threadIdx.x; i < nb; i += BLK) {
+  for (int64_t i = nch * K + gtid<BLK>(); i < nb; i += BLK) {
     const double n1[1] = {src.at(i)};
     const double w1[1] = {1.0};
     double l1[1];
     chunk_1d<NG, BKG, OBJ, GRAD, F32BIN, false>(M, lut, fma(static_cast<double>(i), hx, x0), n1, w1,
                                                 acc, flags, l1);
   }
-  block_sum<NV, BLK / 64>(acc, flags, sm.tot, &sm.totf, reinterpret_cast<double(*)[NV]>(sm.red),
+  group_sum<NV, BLK>(acc, flags, sm.tot, &sm.totf, reinterpret_cast<double(*)[NV]>(sm.red),
                           sm.redf);
-  if (threadIdx.x >= 1 && threadIdx.x < NV) sm.tot[threadIdx.x] *= M.final_factor(threadIdx.x);
-  if (threadIdx.x == 0 && (sm.totf & ST_DOMAIN)) sm.tot[0] = __builtin_inf();
-  __syncthreads();
+  if (gtid<BLK>() >= 1 && gtid<BLK>() < NV) sm.tot[gtid<BLK>()] *= M.final_factor(gtid<BLK>());
+  if (gtid<BLK>() == 0 && (sm.totf & ST_DOMAIN)) sm.tot[0] = __builtin_inf();
+  gsync<BLK>();
 }
 
 // mu(x) and dmu/dtheta by their closed forms, one exp per Gaussian (the
@@ -170,8 +210,8 @@ __device__ __forceinline__ double mu_partials(const Model1D<NG, BKG>& M, double 
 // upper triangle is accumulated kFisherPass entries per pass over the bins
 // and written symmetrically into sm.H.
 template <int NG, int BKG, int OBJ, int PASS, int BLK>
-__device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const CountsSrc& src,
-                            int64_t nb, double x0, double hx) {
+__device__ __forceinline__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG, BLK>& sm,
+    const CountsSrc& src, int64_t nb, double x0, double hx) {
   constexpr int P = FitShared<NG, BKG, BLK>::P;
   constexpr TriIndex<P> tri{};
   constexpr int E0 = PASS * kFisherPass;
@@ -182,7 +222,7 @@ __device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-    for (int64_t i = threadIdx.x; i < nb; i += BLK) {
+    for (int64_t i = gtid<BLK>(); i < nb; i += BLK) {
       double v[P];
       const double mu = mu_partials(M, fma(static_cast<double>(i), hx, x0), v);
       double c;
@@ -197,11 +237,11 @@ __device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const
         for (int q = 0; q < NQ; ++q) acc[q] = fma(c * v[tri.a[E0 + q]], v[tri.b[E0 + q]], acc[q]);
       }
     }
-    block_sum<NQ, BLK / 64>(acc, 0, sm.ftot, &sm.ftotf, reinterpret_cast<double(*)[NQ]>(sm.fred), sm.fredf);
-    if (threadIdx.x < NQ) {
-      const int r = tri.a[E0 + threadIdx.x], c = tri.b[E0 + threadIdx.x];
-      sm.H[r * P + c] = sm.ftot[threadIdx.x];
-      sm.H[c * P + r] = sm.ftot[threadIdx.x];
+    group_sum<NQ, BLK>(acc, 0, sm.ftot, &sm.ftotf, reinterpret_cast<double(*)[NQ]>(sm.fred), sm.fredf);
+    if (gtid<BLK>() < NQ) {
+      const int r = tri.a[E0 + gtid<BLK>()], c = tri.b[E0 + gtid<BLK>()];
+      sm.H[r * P + c] = sm.ftot[gtid<BLK>()];
+      sm.H[c * P + r] = sm.ftot[gtid<BLK>()];
     }
     fisher_pass<NG, BKG, OBJ, PASS + 1, BLK>(a, sm, src, nb, x0, hx);
   }
@@ -214,22 +254,22 @@ __device__ void fisher_pass(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const
 // identity when F_u is not safely positive definite or anything is not
 // finite.  Returns whether the inverse was taken.
 template <int NG, int BKG, int BLK>
-__device__ bool fisher_start(FitShared<NG, BKG, BLK>& sm, int nf) {
+__device__ __forceinline__ bool fisher_start(FitShared<NG, BKG, BLK>& sm, int nf) {
   constexpr int P = FitShared<NG, BKG, BLK>::P;
-  const int tid = threadIdx.x;
-  __syncthreads();
+  const int tid = gtid<BLK>();
+  gsync<BLK>();
   for (int t = tid; t < nf * nf; t += BLK) {
     const int r = t / nf, c = t % nf;
     sm.Lc[r * P + c] = sm.sig[sm.fidx[r]] * sm.sig[sm.fidx[c]] * sm.H[sm.fidx[r] * P + sm.fidx[c]];
   }
-  __syncthreads();
+  gsync<BLK>();
   if (tid == 0) {
     double dmax = 0.0;
     for (int r = 0; r < nf; ++r) dmax = fmax(dmax, sm.Lc[r * P + r]);
     sm.dmax = dmax;
     sm.chol_ok = (dmax > 0.0 && __builtin_isfinite(dmax)) ? 1 : 0;
   }
-  __syncthreads();
+  gsync<BLK>();
   const double dmax = sm.dmax;
   for (int j = 0; j < nf && sm.chol_ok; ++j) {
     if (tid == 0) {
@@ -238,13 +278,13 @@ __device__ bool fisher_start(FitShared<NG, BKG, BLK>& sm, int nf) {
       if (!(d > 1e-12 * dmax) || !__builtin_isfinite(d)) sm.chol_ok = 0;
       else sm.Lc[j * P + j] = sqrt(d);
     }
-    __syncthreads();
+    gsync<BLK>();
     if (sm.chol_ok && tid > j && tid < nf) {
       double v = sm.Lc[tid * P + j];
       for (int k = 0; k < j; ++k) v -= sm.Lc[tid * P + k] * sm.Lc[j * P + k];
       sm.Lc[tid * P + j] = v / sm.Lc[j * P + j];
     }
-    __syncthreads();
+    gsync<BLK>();
   }
   if (sm.chol_ok) {
     if (tid < nf) {  // column tid of inv(L), into the lower triangle of H
@@ -255,7 +295,7 @@ __device__ bool fisher_start(FitShared<NG, BKG, BLK>& sm, int nf) {
         sm.H[i * P + c] = v / sm.Lc[i * P + i];
       }
     }
-    __syncthreads();
+    gsync<BLK>();
     for (int t = tid; t < nf * nf; t += BLK) {
       const int r = t / nf, c = t % nf;
       double v = 0.0;
@@ -263,14 +303,14 @@ __device__ bool fisher_start(FitShared<NG, BKG, BLK>& sm, int nf) {
       sm.Lc[r * P + c] = v;
       if (!__builtin_isfinite(v)) sm.chol_ok = 0;
     }
-    __syncthreads();
+    gsync<BLK>();
   }
   const bool ok = sm.chol_ok != 0;
   for (int t = tid; t < P * P; t += BLK) {
     const int r = t / P, c = t % P;
     sm.H[t] = (ok && r < nf && c < nf) ? sm.Lc[r * P + c] : (r == c ? 1.0 : 0.0);
   }
-  __syncthreads();
+  gsync<BLK>();
   return ok;
 }
 
@@ -294,18 +334,18 @@ __device__ __forceinline__ double dot_lds(const double* x, const double* y, int 
 
 // f(u) and g_u = sigma * dL/dtheta at theta = theta0 + sigma * u.
 template <int NG, int BKG, int OBJ, int BLK>
-__device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
-                               const CountsSrc& src, const double* uu, double* gout, bool f32,
-                               int64_t nb, double x0, double hx) {
+__device__ __forceinline__ double wg_objective(const FitArgs& a, FitShared<NG, BKG, BLK>& sm,
+    const double2* lut, const CountsSrc& src, const double* uu, double* gout, bool f32, int64_t nb,
+    double x0, double hx) {
   constexpr int P = FitShared<NG, BKG, BLK>::P;
-  const int tid = threadIdx.x;
+  const int tid = gtid<BLK>();
   if (tid < P) sm.th[tid] = sm.th0[tid];
-  __syncthreads();
+  gsync<BLK>();
   if (tid < sm.nf) {
     const int k = sm.fidx[tid];
     sm.th[k] = fma(sm.sig[k], uu[tid], sm.th0[k]);
   }
-  __syncthreads();
+  gsync<BLK>();
   if (f32)
     wg_eval<NG, BKG, OBJ, true, true, BLK>(a, sm, lut, src, nb, x0, hx);
   else
@@ -315,28 +355,27 @@ __device__ double wg_objective(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, co
     gout[tid] = sm.sig[k] * sm.tot[1 + k];
   }
   const double f = sm.tot[0];
-  __syncthreads();
+  gsync<BLK>();
   return f;
 }
 
 // f(u) alone (FP64 bins): the value the finite-difference gradient and its
 // line search need.
 template <int NG, int BKG, int OBJ, int BLK>
-__device__ double wg_value(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
-                           const CountsSrc& src, const double* uu, int64_t nb, double x0,
-                           double hx) {
+__device__ __forceinline__ double wg_value(const FitArgs& a, FitShared<NG, BKG, BLK>& sm,
+    const double2* lut, const CountsSrc& src, const double* uu, int64_t nb, double x0, double hx) {
   constexpr int P = FitShared<NG, BKG, BLK>::P;
-  const int tid = threadIdx.x;
+  const int tid = gtid<BLK>();
   if (tid < P) sm.th[tid] = sm.th0[tid];
-  __syncthreads();
+  gsync<BLK>();
   if (tid < sm.nf) {
     const int k = sm.fidx[tid];
     sm.th[k] = fma(sm.sig[k], uu[tid], sm.th0[k]);
   }
-  __syncthreads();
+  gsync<BLK>();
   wg_eval<NG, BKG, OBJ, false, false, BLK>(a, sm, lut, src, nb, x0, hx);
   const double f = sm.tot[0];
-  __syncthreads();
+  gsync<BLK>();
   return f;
 }
 
@@ -346,10 +385,10 @@ __device__ double wg_value(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const 
 constexpr double kFdStep = 1e-4;
 
 template <int NG, int BKG, int OBJ, int BLK>
-__device__ void wg_fd_grad(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
-                           const CountsSrc& src, const double* uu, double* gout, int64_t nb,
-                           double x0, double hx) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void wg_fd_grad(const FitArgs& a, FitShared<NG, BKG, BLK>& sm,
+    const double2* lut, const CountsSrc& src, const double* uu, double* gout, int64_t nb, double x0,
+    double hx) {
+  const int tid = gtid<BLK>();
   const int nf = sm.nf;
   for (int q = 0; q < nf; ++q) {
     const double h = kFdStep * fmax(1.0, fabs(uu[q]));
@@ -360,15 +399,15 @@ __device__ void wg_fd_grad(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const 
     const double fm = wg_value<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.up, nb, x0, hx);
     if (tid == 0) gout[q] = (fp - fm) / (up - um);
   }
-  __syncthreads();
+  gsync<BLK>();
 }
 
 template <int NG, int BKG, int OBJ, int BLK>
-__device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const double2* lut,
-                        uint32_t* cache, int b) {
+__device__ __forceinline__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm,
+    const double2* lut, uint32_t* cache, int cache_cap, int b) {
   constexpr int P = FitShared<NG, BKG, BLK>::P;
   constexpr int NB = Shape1D<NG, BKG>::NB;
-  const int tid = threadIdx.x;
+  const int tid = gtid<BLK>();
   const int64_t off = a.offsets[b];
   const int64_t nb = a.offsets[b + 1] - off;
   const double lo = a.ranges[2 * b], hi = a.ranges[2 * b + 1];
@@ -380,20 +419,20 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
       a.iters[b] = 0;
       a.nevals[b] = 0;
     }
-    __syncthreads();
+    gsync<BLK>();
     return;
   }
   const double hx = (hi - lo) / static_cast<double>(nb);
   const double x0 = lo + 0.5 * hx;
   CountsSrc src{nullptr, a.counts, a.dtype, off};
-  if (a.dtype == DT_U32 && nb <= a.cache_bins) {  // keep the counts in LDS for all evaluations
+  if (a.dtype == DT_U32 && nb <= cache_cap) {  // keep the counts in LDS for all evaluations
     const uint32_t* g = static_cast<const uint32_t*>(a.counts) + off;
     for (int64_t i = tid; i < nb; i += BLK) cache[i] = g[i];
     src.lds = cache;
   }
 
   if (tid < P) sm.th0[tid] = a.theta0[static_cast<int64_t>(b) * P + tid];
-  __syncthreads();
+  gsync<BLK>();
   if (tid == 0) {
     const double rx = hi - lo;
     int k = 0;
@@ -410,7 +449,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
   }
   if (tid < P) sm.u[tid] = 0.0;
   for (int t = tid; t < P * P; t += BLK) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
-  __syncthreads();
+  gsync<BLK>();
   const int nf = sm.nf;
   bool first = true;
   if (a.hessian_init == 1 && nf > 0) {
@@ -441,7 +480,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
         sm.pv[tid] = -hg;
         sm.tmp[tid] = sm.g[tid] * hg;
       }
-      __syncthreads();
+      gsync<BLK>();
       double edm = 0.0;
       edm = dot_lds<P>(sm.tmp, nullptr, nf);
       edm *= 0.5;
@@ -464,11 +503,11 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
       double slope = 0.0;
       slope = dot_lds<P>(sm.g, sm.pv, nf);
       if (!(slope < 0.0)) {  // H lost positive definiteness: restart from I
-        __syncthreads();
+        gsync<BLK>();
         for (int t = tid; t < P * P; t += BLK) sm.H[t] = (t / P == t % P) ? 1.0 : 0.0;
         if (tid < nf) sm.pv[tid] = -sm.g[tid];
         first = true;
-        __syncthreads();
+        gsync<BLK>();
         slope = 0.0;
         slope = -dot_lds<P>(sm.g, sm.g, nf);
       }
@@ -476,7 +515,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
       bool accepted = false;
       for (int ls = 0; ls < a.ls_max; ++ls) {
         if (tid < nf) sm.un[tid] = sm.u[tid] + alpha * sm.pv[tid];
-        __syncthreads();
+        gsync<BLK>();
         fn = fd ? wg_value<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.un, nb, x0, hx)
                 : wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.un, sm.gn, f32, nb, x0, hx);
         ++nev;
@@ -499,7 +538,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
         sm.sv[tid] = sm.un[tid] - sm.u[tid];
         sm.yv[tid] = sm.gn[tid] - sm.g[tid];
       }
-      __syncthreads();
+      gsync<BLK>();
       const double sy = dot_lds<P>(sm.sv, sm.yv, nf);
       const double yy = dot_lds<P>(sm.yv, sm.yv, nf);
       const double ss = dot_lds<P>(sm.sv, sm.sv, nf);
@@ -508,14 +547,14 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
           const double gam = sy / yy;
           for (int t = tid; t < nf * nf; t += BLK) sm.H[(t / nf) * P + t % nf] *= gam;
           first = false;
-          __syncthreads();
+          gsync<BLK>();
         }
         if (tid < nf) {
           double hy = 0.0;
           hy = dot_lds<P>(&sm.H[tid * P], sm.yv, nf);
           sm.Hy[tid] = hy;
         }
-        __syncthreads();
+        gsync<BLK>();
         double yHy = 0.0;
         yHy = dot_lds<P>(sm.yv, sm.Hy, nf);
         const double rho = 1.0 / sy;
@@ -529,7 +568,7 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
         sm.u[tid] = sm.un[tid];
         sm.g[tid] = sm.gn[tid];
       }
-      __syncthreads();
+      gsync<BLK>();
       f = fn;
     }
   }
@@ -537,12 +576,12 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
   if (f32 && __builtin_isfinite(f)) nll = wg_objective<NG, BKG, OBJ, BLK>(a, sm, lut, src, sm.u, sm.gn, false, nb, x0, hx);
   // final parameters, canonicalised
   if (tid < P) sm.th[tid] = sm.th0[tid];
-  __syncthreads();
+  gsync<BLK>();
   if (tid < nf) {
     const int k = sm.fidx[tid];
     sm.th[k] = fma(sm.sig[k], sm.u[tid], sm.th0[k]);
   }
-  __syncthreads();
+  gsync<BLK>();
   if (tid == 0) {
     for (int g = 0; g < NG; ++g) sm.th[3 * g + 2] = fabs(sm.th[3 * g + 2]);
     for (int p = 1; p < NG; ++p)
@@ -557,26 +596,61 @@ __device__ void fit_one(const FitArgs& a, FitShared<NG, BKG, BLK>& sm, const dou
     a.iters[b] = it;
     a.nevals[b] = nev;
   }
-  __syncthreads();
+  gsync<BLK>();
   if (tid < P) a.theta_out[static_cast<int64_t>(b) * P + tid] = sm.th[tid];
-  __syncthreads();
+  gsync<BLK>();
+}
+
+// Bytes of dynamic LDS one wave takes in wave mode: its fit state, then an
+// LDS copy of up to wave_bins u32 counts.
+template <int NG, int BKG>
+constexpr size_t wave_slot_bytes(int wave_bins) {
+  return ((sizeof(FitShared<NG, BKG, 64>) + 15) / 16) * 16 + 4 * static_cast<size_t>(wave_bins);
 }
 
 template <int NG, int BKG, int OBJ, int BLK>
 __global__ __launch_bounds__(BLK) void k_fit(FitArgs a) {
   __shared__ FitShared<NG, BKG, BLK> sm;
   __shared__ double2 lut[OBJ == OBJ_POISSON ? kLogLut : 1];
-  extern __shared__ uint32_t cache[];  // a.cache_bins entries
+  // the workgroup's count cache, or the waves' slots
+  extern __shared__ __attribute__((aligned(16))) uint32_t cache[];
   const int tid = threadIdx.x;
   if constexpr (OBJ == OBJ_POISSON) log_lut_load(lut, a.log_lut);
+  // wave mode needs the longest-first order: the first histogram of at most
+  // wave_bins bins is followed by smaller ones only
+  const bool waves = a.wave_bins > 0 && a.sorted;
+  int h;
   for (;;) {
     if (tid == 0) sm.h = static_cast<int>(atomicAdd(&a.counters[0], 1u));
     __syncthreads();
-    const int h = sm.h;
+    h = sm.h;
     __syncthreads();
     if (h >= a.B) break;
-    fit_one<NG, BKG, OBJ, BLK>(a, sm, lut, cache, a.sorted ? a.order[h] : h);
+    const int b = a.sorted ? a.order[h] : h;
+    if (waves && a.offsets[b + 1] - a.offsets[b] <= a.wave_bins) break;
+    fit_one<NG, BKG, OBJ, BLK>(a, sm, lut, cache, a.cache_bins, b);
   }
+  if (waves && h < a.B) {
+    // from here on every wave fits its own histograms: wave 0 the one just
+    // taken, the others and every later one from the queue
+    const int w = tid >> 6;
+    char* slot = reinterpret_cast<char*>(cache) + w * wave_slot_bytes<NG, BKG>(a.wave_bins);
+    auto& sw = *reinterpret_cast<FitShared<NG, BKG, 64>*>(slot);
+    uint32_t* wc = reinterpret_cast<uint32_t*>(slot + wave_slot_bytes<NG, BKG>(0));
+    int hw = h;
+    if (w != 0) {
+      int t = 0;
+      if ((tid & 63) == 0) t = static_cast<int>(atomicAdd(&a.counters[0], 1u));
+      hw = __shfl(t, 0);
+    }
+    while (hw < a.B) {
+      fit_one<NG, BKG, OBJ, 64>(a, sw, lut, wc, a.wave_bins, a.order[hw]);
+      int t = 0;
+      if ((tid & 63) == 0) t = static_cast<int>(atomicAdd(&a.counters[0], 1u));
+      hw = __shfl(t, 0);
+    }
+  }
+  __syncthreads();  // every wave is past the queue before the workgroup leaves
   // the last workgroup to leave re-arms the queue for the next launch
   if (tid == 0) {
     __threadfence();
@@ -590,7 +664,9 @@ __global__ __launch_bounds__(BLK) void k_fit(FitArgs a) {
 
 template <int NG, int BKG, int OBJ, int BLK>
 hipError_t launch_fit_kernel(const FitArgs& a, int grid, hipStream_t s, int* max_cache) {
-  if (grid <= 0) {  // report the largest dynamic LDS cache that still fits
+  if (grid <= 0) {
+    // grid 0: the largest dynamic LDS cache (u32 bins) that still fits;
+    // grid -1: the largest wave_bins whose per-wave slots fit
     hipFuncAttributes attr;
     hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k_fit<NG, BKG, OBJ, BLK>));
     if (e != hipSuccess) return e;
@@ -599,11 +675,21 @@ hipError_t launch_fit_kernel(const FitArgs& a, int grid, hipStream_t s, int* max
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
-    *max_cache = static_cast<int>((lds - static_cast<int>(attr.sharedSizeBytes)) / 4);
+    const long free_bytes = static_cast<long>(lds) - static_cast<long>(attr.sharedSizeBytes);
+    if (grid == 0) {
+      *max_cache = static_cast<int>(free_bytes / 4);
+    } else {
+      const long per_wave = free_bytes / (BLK / 64) - static_cast<long>(wave_slot_bytes<NG, BKG>(0));
+      *max_cache = per_wave > 0 ? static_cast<int>(per_wave / 4) : 0;
+    }
     return hipSuccess;
   }
-  hipLaunchKernelGGL((k_fit<NG, BKG, OBJ, BLK>), dim3(grid), dim3(BLK),
-                     sizeof(uint32_t) * static_cast<size_t>(a.cache_bins), s, a);
+  size_t dyn = sizeof(uint32_t) * static_cast<size_t>(a.cache_bins);
+  if (a.wave_bins > 0) {
+    const size_t w = (BLK / 64) * wave_slot_bytes<NG, BKG>(a.wave_bins);
+    dyn = w > dyn ? w : dyn;
+  }
+  hipLaunchKernelGGL((k_fit<NG, BKG, OBJ, BLK>), dim3(grid), dim3(BLK), dyn, s, a);
   return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ struct FitArgs {
   int32_t cache_bins;      // LDS cache capacity (u32 counts); 0 = no cache
   int32_t hessian_init;    // 0 identity, 1 inverse expected Hessian at theta0
   int32_t fd_grad;         // 1: central-difference gradient (FP64 bins)
+  int32_t wave_bins;       // histograms of at most this many bins are fitted one per wave (0: off)
 };
 
 // Device scratch of the fitter, owned by the context.  `order` grows with B;
@@ -53,6 +54,7 @@ struct FitScratch {
   int wg_per_cu = 2;   // persistent workgroups per CU
   int cache_bins = 0;  // histograms with at most this many u32 bins live in LDS
   int block = 256;     // threads per workgroup (256 or 512)
+  int wave_bins = 0;   // one wave per histogram of at most this many bins (0: off)
 };
 
 hipError_t fit_scratch_init(FitScratch* s);
@@ -64,5 +66,9 @@ hipError_t launch_fit(int n_gauss, int bkg, FitArgs a, int num_cu, FitScratch* s
 // Largest LDS cache (in u32 bins) a fit workgroup of `block` threads can
 // hold for this model and objective next to its own state.
 int fit_max_cache_bins(int n_gauss, int bkg, int obj, int block);
+
+// Largest wave_bins whose per-wave slots (fit state + counts) fit in the
+// LDS a workgroup of `block` threads has next to its own state.
+int fit_max_wave_bins(int n_gauss, int bkg, int obj, int block);
 
 }  // namespace hf

@@ -83,6 +83,9 @@ def test_newer_entry_points_reject_null_context_without_gpu(lib):
                                  None) == -1
     assert lib.nll_unbinned(None, None, None, 4, 0.0, 1.0, None, None, None, None, None,
                             None) == -1
+    assert lib.hf_fit_set_wave_bins(None, 256) == -1
+    assert lib.hf_fit_get_wave_bins(None) == -1
+    assert lib.hf_fit_max_wave_bins(None, None, 2, 256) == -1
 
 
 def test_bin_average_flag_is_validated_on_the_host(lib):

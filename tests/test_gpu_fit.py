@@ -314,3 +314,57 @@ def test_finite_difference_fits_reach_the_adjoint_minima(hf, orc, K):
     with pytest.raises(hf.HistfitError):
         run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], c["theta0"],
                 gradient=hf.FINITE_DIFF, objective=2, precision=1)
+
+
+def _sized_subset(B, seed, lo_bins, hi_bins):
+    c = datagen.batch_case(seed=seed, B=B, lo_bins=lo_bins, hi_bins=hi_bins)
+    rng = np.random.default_rng(seed + 77)
+    th0 = c["theta_true"].copy()
+    th0[:, 0] *= 1 + 0.05 * rng.standard_normal(B)
+    th0[:, 1] += 0.3 * th0[:, 2] * rng.standard_normal(B)
+    th0[:, 2] *= 1 + 0.05 * rng.standard_normal(B)
+    th0[:, 3] += 0.05 * rng.standard_normal(B)
+    th0[:, 4] += 0.05 * rng.standard_normal(B)
+    return c, th0
+
+
+@pytest.mark.parametrize("blk", [256, 512])
+def test_wave_per_small_histogram_matches_oracle(hf, orc, blk):
+    """Once the longest-first queue reaches histograms of at most wave_bins
+    bins, every wave fits its own (state and counts in an LDS slot of its
+    own, wave-level reductions): with it off, at 1024 bins and at the model's
+    limit, with and without the workgroup count cache, in FP64 and FP32 bins,
+    the fits reach the oracle's minima, and a second call (the queue re-armed
+    by the first) gives the same results; a wave_bins above the limit is
+    refused."""
+    c, th0 = _sized_subset(240, seed=41, lo_bins=64, hi_bins=6000)
+    rth, rnll, rst, _, _ = orc.fit_many(orc_model(orc, c["spec"]), 2, c["counts"], c["offsets"],
+                                        c["ranges"], th0, nthreads=8, hessian_init=1)
+    m = hf.Model.from_spec(c["spec"])
+    cap_w = hf.fit_max_wave_bins(m, hf.POISSON, blk)
+    cap_c = hf.fit_max_cache_bins(m, hf.POISSON, blk)
+    assert cap_w >= 2048
+    try:
+        for wb in (0, 1024, cap_w):
+            for cb in (0, cap_c):
+                hf.fit_set_tuning(2, cb, blk)
+                hf.fit_set_wave_bins(wb)
+                assert hf.fit_get_wave_bins() == wb
+                for prec in (0, 1):
+                    kw = dict(objective=2, precision=prec, polish_edm=1e-3 if prec else 0.0)
+                    th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], c["offsets"],
+                                                  c["ranges"], th0, **kw)
+                    both = (st == 0) & (rst == 0)
+                    assert both.mean() > 0.9, (wb, cb, prec, st)
+                    assert np.all(np.abs(nll - rnll)[both] < 1e-6), (wb, cb, prec)
+                    again = run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], th0, **kw)
+                    for x, y in zip((th, nll, st, it, ne), again):
+                        np.testing.assert_array_equal(x, y)
+        hf.fit_set_wave_bins(cap_w + 1)
+        with pytest.raises(hf.HistfitError):
+            run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], th0)
+        with pytest.raises(hf.HistfitError):
+            hf.fit_set_wave_bins(-1)
+    finally:
+        hf.fit_set_wave_bins(0)
+        hf.fit_set_tuning(2, 0, 256)
