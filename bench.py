@@ -180,12 +180,15 @@ def main():
     ap.add_argument("--train-fits", type=int, default=1_000_000,
                     help="learned workload: plain fits the initialiser is trained on")
     ap.add_argument("--epochs", type=int, default=8, help="learned workload: training epochs")
-    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "learned", "gradient",
-                                           "fisher", "gradmap", "unbinned", "binavg", "edges"],
+    ap.add_argument("--workload", choices=["large1d", "hist2d", "fits", "smallfits", "learned",
+                                           "gradient", "fisher", "gradmap", "unbinned", "binavg",
+                                           "edges"],
                     default="large1d",
                     help="large1d: the 1e7-bin NLL+gradient (default); hist2d: 2048^2 weighted "
                          "NLL+gradient+weight gradient; fits: 4096 uneven histograms fitted by "
-                         "fit_batch; learned: plain vs learned-initialiser fits of that batch; "
+                         "fit_batch; smallfits: 16384 histograms of 128..1024 bins, with and "
+                         "without one wave per histogram; learned: plain vs "
+                         "learned-initialiser fits of the 4096 batch; "
                          "gradient: fits with the reverse-mode gradient vs central differences "
                          "for 1..4 Gaussians; fisher: the expected Hessian of the 1e7-bin "
                          "workload (and of the 2048^2 one); gradmap: the elementwise Gaussian "
@@ -226,6 +229,8 @@ def main():
         return bench_hist2d(args, hf, datagen, np, torch, dev)
     if args.workload == "fits":
         return bench_fits(args, hf, datagen, np, torch, dev)
+    if args.workload == "smallfits":
+        return bench_smallfits(args, hf, datagen, np, torch, dev)
     if args.workload == "learned":
         return bench_learned(args, hf, datagen, np, torch, dev)
     if args.workload == "gradient":
@@ -872,6 +877,47 @@ def bench_fits(args, hf, datagen, np, torch, dev):
                           scaling="weak", vs_baseline=None, dtype=sec.pop("dtype"),
                           data="synthetic", config=dict(cfg, **sec), cpu_baseline=cpu)),
           flush=True)
+
+
+def bench_smallfits(args, hf, datagen, np, torch, dev):
+    """16384 histograms of 128..1024 bins (log-uniform; Gauss + exponential
+    background, Poisson) from the default starts, FP32 bins + FP64 polish:
+    the autotuned shape (which includes the size below which every wave fits
+    a histogram of its own) against the same shape with one workgroup per
+    histogram; fits/s counts fits within 1e-6 of the FP64-bin fit."""
+    from paper_2203_06139_amd.autotune import tune_fit
+    c = datagen.batch_case(seed=11, B=16384, lo_bins=128, hi_bins=1024)
+    B = len(c["nbins"])
+    counts = torch.from_numpy(c["counts"].view(np.int32)).to(dev)
+    off = torch.as_tensor(c["offsets"], device=dev)
+    rg = torch.as_tensor(c["ranges"], device=dev)
+    m = hf.Model.from_spec(c["spec"])
+    t0 = hf.default_starts(counts, off, rg, m)
+    best, _ = tune_fit(counts, off, rg, m, t0, precision=hf.FP32_BIN, sample=B, use_cache=False)
+    log("autotuned: %s" % best)
+    kw = dict(objective=hf.POISSON, precision=hf.FP32_BIN, polish_edm=best["polish_edm"])
+    ref = hf.fit_batch(counts, off, rg, m, t0, objective=hf.POISSON, precision=hf.FP64)
+    steps = max(1, min(args.steps, 20))
+    res = {}
+    for name, wb in (("workgroup_per_histogram", 0), ("tuned", best["wave_bins"])):
+        hf.fit_set_wave_bins(wb)
+        out = hf.fit_batch(counts, off, rg, m, t0, **kw)
+        ms = time_graph(torch, lambda k: hf.fit_batch(counts, off, rg, m, t0, out=out, **kw), steps)
+        ok = int(((out.status == 0) & (ref.status == 0) & ((out.nll - ref.nll).abs() < 1e-6))
+                 .sum().item())
+        res[name] = dict(wave_bins=wb, ms=ms, agreeing=ok, fits_per_s=ok / (ms * 1e-3))
+    hf.fit_set_wave_bins(0)
+    t = res["tuned"]
+    print(json.dumps(dict(
+        metric="fits/s at |dNLL|<1e-6", value=t["fits_per_s"], unit="fits/s", n_gpus=1,
+        steps=steps, warmup=1, ms_per_step=t["ms"], higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32-bin/f64-acc", data="synthetic",
+        config=dict(workload="16384 1D histograms, 128..1024 bins (log-uniform), Gauss + "
+                             "exponential background, Poisson, default starts, one "
+                             "graph-replayed fit_batch launch", histograms=B,
+                    total_bins=int(c["offsets"][-1])),
+        tuning=best, modes=res,
+        speedup=res["workgroup_per_histogram"]["ms"] / t["ms"])), flush=True)
 
 
 def bench_learned(args, hf, datagen, np, torch, dev):
