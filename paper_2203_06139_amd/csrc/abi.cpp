@@ -289,10 +289,11 @@ int run_objective(hf_ctx* c, const hf_hist* h, const hf_model* m, int32_t obj, i
     if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
     it = c->occupancy.emplace(fn, std::make_pair(occ < 1 ? 1 : occ, block)).first;
   }
-  // The 2D kernel runs one block per CU even where its registers would allow
-  // two: measured on the 2048^2 workload, 41.0 us at one block per CU and
-  // 52.0 us at two.
-  const int occ = two_d ? 1 : it->second.first;
+  // The 2D kernel runs at most two blocks per CU: measured on the 2048^2
+  // workload with the two-kernel completion, 27.4 us at one block per CU,
+  // 24.2 at two, 24.3 at three and 26.6 at four (with the one-kernel
+  // completion one block had been faster, 41.0 against 52.0 us).
+  const int occ = two_d ? std::min(2, it->second.first) : it->second.first;
   const int block = it->second.second;
   const int per_cu = c->blocks_per_cu > 0 ? c->blocks_per_cu : occ;
   // 2D work items are 16-bin pieces of one row (a row's tail is a short piece)
