@@ -544,7 +544,9 @@ HF_EXPORT int nll_unbinned(hf_ctx* c, const double* events, const float* weights
   a.log_lut = c->log_lut;
   const bool vec = aligned16(events) && (reinterpret_cast<uintptr_t>(weights) & 7u) == 0;
   int grid = 0;
-  hipError_t e = fn(a, vec, c->num_cu, kMaxGrid, reinterpret_cast<hipStream_t>(stream), &grid);
+  // HF_BLOCKS_PER_CU caps the blocks per CU here as for the binned kernels
+  const int cap = c->blocks_per_cu > 0 ? std::min(kMaxGrid, c->num_cu * c->blocks_per_cu) : kMaxGrid;
+  hipError_t e = fn(a, vec, c->num_cu, cap, reinterpret_cast<hipStream_t>(stream), &grid);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   hf::FinishArgs f{};
   f.part = c->part;
