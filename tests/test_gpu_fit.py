@@ -115,19 +115,29 @@ def test_fisher_start_cuts_iterations(hf):
     assert r1.iters.float().mean().item() < 0.5 * r0.iters.float().mean().item()
 
 
-def test_bad_histograms_and_status_codes(hf):
+@pytest.mark.parametrize("waves", [False, True])
+def test_bad_histograms_and_status_codes(hf, waves):
+    """Status codes of fit_batch, with one workgroup per histogram and with
+    every histogram (empty ones included) fitted by a wave of its own."""
     c, th0 = _subset(4)
+    m = hf.Model.from_spec(c["spec"])
+    wave_bins = hf.fit_max_wave_bins(m, hf.POISSON, 256) if waves else 0
+    assert wave_bins == 0 or wave_bins >= max(np.diff(c["offsets"]))
     off = c["offsets"].copy()
     off[2] = off[1]  # histogram 1 empty
     ranges = c["ranges"].copy()
     ranges[3] = (1.0, 1.0)  # histogram 3: empty range
-    th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], off, ranges, th0)
-    assert st[1] == hf.FIT_BADHIST and st[3] == hf.FIT_BADHIST
-    np.testing.assert_array_equal(th[1], th0[1])
-    assert st[0] == hf.FIT_CONVERGED
-    th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], th0,
-                                  max_iter=1)
-    assert np.all(st == hf.FIT_MAXITER) and np.all(it == 1)
+    try:
+        hf.fit_set_wave_bins(wave_bins)
+        th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], off, ranges, th0)
+        assert st[1] == hf.FIT_BADHIST and st[3] == hf.FIT_BADHIST
+        np.testing.assert_array_equal(th[1], th0[1])
+        assert st[0] == hf.FIT_CONVERGED
+        th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], c["offsets"], c["ranges"], th0,
+                                      max_iter=1)
+        assert np.all(st == hf.FIT_MAXITER) and np.all(it == 1)
+    finally:
+        hf.fit_set_wave_bins(0)
 
 
 def test_fit_batch_repeatable_and_graph_replay(hf):
