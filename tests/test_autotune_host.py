@@ -102,3 +102,14 @@ def test_wave_stage_skips_disagreeing_sizes(monkeypatch):
     best, _ = autotune.tune_fit(*_batch()[:3], hf.Model(hf.GAUSS_EXP, 1), _batch()[3], sample=8,
                                 use_cache=False)
     assert best["wave_bins"] == 0 and state["waves"] == 0
+
+
+def test_wave_stage_needs_a_clear_gain(monkeypatch):
+    """A wave_bins setting within the margin of the best time (here at most
+    0.5% faster) is not taken: one wave per histogram slows each of those
+    fits, so only a clear gain on the timed batch counts."""
+    state = _install(monkeypatch, agreeing={(256, 1)}, wave_gain=0.005)
+    best, results = autotune.tune_fit(*_batch()[:3], hf.Model(hf.GAUSS_EXP, 1), _batch()[3],
+                                      sample=8, use_cache=False)
+    assert any(r.get("wave_bins", 0) == 1024 and r["ms"] < 1.0 for r in results)
+    assert best["wave_bins"] == 0 and state["waves"] == 0
