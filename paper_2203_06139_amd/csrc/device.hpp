@@ -229,8 +229,7 @@ __device__ __forceinline__ void store_relaxed(int* p, int v) {
 }
 
 // Grid-wide deterministic completion of a multi-value sum in one kernel
-// (used where the outputs are not the objective's: the expected Hessian and
-// the gradient map's shared sums).  Every block publishes its block totals
+// (used for the gradient map's shared sums, which its own kernel writes).  Every block publishes its block totals
 // to part[k * G + block]; the block that takes the last ticket sums the G
 // partials of each component in block order (strided over its threads, then
 // the fixed block_sum tree) and returns true with the grand totals in

@@ -76,6 +76,17 @@ struct FitShared {
 // 16-byte vectors instead of one by one, 12.1 us with 8.
 constexpr int kFitChunkSmall = 4;
 constexpr int kFitChunkLarge = 8;
+// The 8-bin sweep is built where it fits the register budget: 512-thread
+// workgroups (two waves per SIMD by construction) of one Gaussian with no,
+// a constant or an exponential background, which stay below 256 VGPRs
+// without spilling.  With a sloped polynomial background the 8-bin sweep
+// spilled at 512 threads (32-144 bytes per lane), and at 256 threads it
+// took several models to one wave per SIMD (256 VGPRs plus AGPRs), e.g.
+// Gauss + line, Poisson: 0.35 -> 0.46 ms for 512 histograms of 10,000 bins.
+template <int NG, int BKG, int BLK>
+constexpr bool fit_chunk_large() {
+  return BLK == 512 && NG == 1 && (BKG == BKG_NONE || BKG == 0 || BKG == BKG_EXP);
+}
 
 // Where a histogram's counts are read from: the workgroup's LDS cache (u32)
 // or global memory (any dtype).
@@ -193,10 +204,13 @@ __device__ __forceinline__ void wg_eval_k(const FitArgs& a, FitShared<NG, BKG, B
 template <int NG, int BKG, int OBJ, bool F32BIN, bool GRAD, int BLK>
 __device__ __forceinline__ void wg_eval(const FitArgs& a, FitShared<NG, BKG, BLK>& sm,
     const double2* lut, const CountsSrc& src, int64_t nb, double x0, double hx) {
-  if (BLK > 64 && nb >= static_cast<int64_t>(kFitChunkLarge) * BLK)
-    wg_eval_k<NG, BKG, OBJ, F32BIN, GRAD, BLK, kFitChunkLarge>(a, sm, lut, src, nb, x0, hx);
-  else
-    wg_eval_k<NG, BKG, OBJ, F32BIN, GRAD, BLK, kFitChunkSmall>(a, sm, lut, src, nb, x0, hx);
+  if constexpr (fit_chunk_large<NG, BKG, BLK>()) {
+    if (nb >= static_cast<int64_t>(kFitChunkLarge) * BLK) {
+      wg_eval_k<NG, BKG, OBJ, F32BIN, GRAD, BLK, kFitChunkLarge>(a, sm, lut, src, nb, x0, hx);
+      return;
+    }
+  }
+  wg_eval_k<NG, BKG, OBJ, F32BIN, GRAD, BLK, kFitChunkSmall>(a, sm, lut, src, nb, x0, hx);
 }
 
 // mu(x) and dmu/dtheta by their closed forms, one exp per Gaussian (the

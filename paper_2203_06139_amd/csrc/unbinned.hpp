@@ -18,8 +18,8 @@
 //   d/ds = Lambda_g/s + A (z_lo e_lo - z_hi e_hi);
 //   polynomial: d/dc_j = t_scale (t_hi^(j+1) - t_lo^(j+1))/(j+1);
 //   exponential: (hi - lo) E_c S(b1 d), E_c = exp(b0 + b1 t_c), S = sinh(u)/u;
-// thread 0 of every block computes them into LDS during the prologue, and
-// the block that finishes the grid reduction adds them.  Events outside
+// thread 0 of block 0 computes them into LDS during the prologue and adds
+// them to the partials it publishes.  Events outside
 // [lo, hi] are skipped; lambda <= 0 at an event inside is a domain error.
 #pragma once
 
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_nll_unbinned(UnbinnedArgs a) {
   M.init(a.theta, a.t_shift, a.t_scale);
   const bool finite = all_finite(a.theta, S::P);
   if (threadIdx.x == 0) {
-    lambda_terms<NG, BKG>(a, M, lamd);
+    if (blockIdx.x == 0) lambda_terms<NG, BKG>(a, M, lamd);
 #pragma unroll
     for (int k = 0; k <= S::P; ++k) ff[k] = M.final_factor(k);
   }
