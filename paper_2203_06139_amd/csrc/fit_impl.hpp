@@ -18,11 +18,12 @@
 // Finally |s| for every width, Gaussians ordered by mean, and the NLL
 // re-evaluated with FP64 bins.
 //
-// Work split: the whole workgroup evaluates the objective and gradient over
-// the histogram's bins (chunk_1d + block_sum); the O(P^2) BFGS algebra is
-// spread over the first P or P^2 threads; scalar decisions are computed
-// redundantly by every thread from the same LDS values, so control flow
-// stays uniform without extra barriers.
+// Work split: the whole workgroup (or, for small histograms, one wave)
+// evaluates the objective and gradient over the histogram's bins (chunk_1d
+// in 4- or 8-bin chunks, then a fixed-order group sum); the O(P^2) BFGS
+// algebra is spread over the first P or P^2 threads; scalar decisions are
+// computed redundantly by every thread from the same LDS values, so control
+// flow stays uniform without extra barriers.
 #pragma once
 
 #include <float.h>
