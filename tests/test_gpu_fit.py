@@ -378,3 +378,34 @@ def test_wave_per_small_histogram_matches_oracle(hf, orc, blk):
     finally:
         hf.fit_set_wave_bins(0)
         hf.fit_set_tuning(2, 0, 256)
+
+
+def test_eight_bin_sweep_matches_oracle(hf, orc):
+    """512-thread workgroups fit histograms of at least 8 x 512 bins of the
+    Gauss + exponential model with 8-bin chunks (several rounds of the
+    workgroup and ragged tails of chunks and single bins here): with the
+    counts streamed from global memory and read from the LDS cache as
+    16-byte vectors, in FP64 and FP32 bins, the fits reach the oracle's
+    minima, and a 256-thread launch (4-bin chunks) reaches the same ones."""
+    c, th0 = _sized_subset(48, seed=43, lo_bins=4096, hi_bins=40000)
+    nb = np.diff(c["offsets"])
+    assert nb.min() >= 8 * 512 and np.any(nb % 8 != 0) and np.any(nb > 8 * 512 * 4)
+    rth, rnll, rst, _, _ = orc.fit_many(orc_model(orc, c["spec"]), 2, c["counts"], c["offsets"],
+                                        c["ranges"], th0, nthreads=8, hessian_init=1)
+    m = hf.Model.from_spec(c["spec"])
+    try:
+        for blk in (512, 256):
+            cap_c = hf.fit_max_cache_bins(m, hf.POISSON, blk)
+            for cb in (0, cap_c):
+                hf.fit_set_tuning(1, cb, blk)
+                for prec in (0, 1):
+                    kw = dict(objective=2, precision=prec, polish_edm=1e-3 if prec else 0.0)
+                    th, nll, st, it, ne = run_fit(hf, c["spec"], c["counts"], c["offsets"],
+                                                  c["ranges"], th0, **kw)
+                    both = (st == 0) & (rst == 0)
+                    assert both.mean() > 0.9, (blk, cb, prec, st, rst)
+                    assert np.all(np.abs(nll - rnll)[both] < 1e-6), (blk, cb, prec)
+                    scale = np.maximum(np.abs(rth[both]), 1e-3)
+                    assert np.all(np.abs(th[both] - rth[both]) <= 1e-3 * scale), (blk, cb, prec)
+    finally:
+        hf.fit_set_tuning(2, 0, 256)
