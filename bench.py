@@ -347,6 +347,7 @@ def main():
     result["roofline"] = dict(bound="alu", achieved=achieved, peak=FP64_VEC_PEAK_TFLOPS,
                               unit="TFLOP/s", frac=achieved / FP64_VEC_PEAK_TFLOPS, traffic=traffic,
                               flops_per_bin=FLOPS_PER_BIN,
+                              timed="one call: the main kernel and its finishing kernel",
                               hbm_gbs=BYTES_PER_BIN * NBINS / (ms_per_step * 1e-3) / 1e9,
                               hbm_frac=BYTES_PER_BIN * NBINS / (ms_per_step * 1e-3) / 1e9 /
                               HBM_PEAK_GBS)
