@@ -318,12 +318,16 @@ hipError_t rebin_lognorm(int B, const void* counts, int dtype, const int64_t* of
 //     of counts over [i - W, i + W] (first such i on ties);
 //   width: walking out from the peak while 2 e >= e_max, the half-maximum
 //     bounds give the FWHM.
-// Each thread takes a contiguous segment of positions and slides the window
-// sum along it (S(i+1) = S(i) + c[i+W+1] - c[i-W]), so the work is linear in
-// nb; the walk becomes a search for the nearest positions left and right of
-// the peak with 2 e < e_max.  Sums of integer-valued counts are exact in
-// FP64 in any order, so every decision matches a direct evaluation; the
-// excess is evaluated without FMA contraction (separate products and sums).
+// The window positions are split among the block's four waves in
+// contiguous ranges; a wave walks its range 64 positions per step, lane l
+// at position s + l, with coalesced loads: the window sum at position i is
+// the sum at the range's first position plus the lane prefix sum of the
+// differences c[i + W] - c[i - W - 1] (S(i) - S(i - 1)).  Sums of
+// integer-valued counts are exact in FP64 in any order, so every window sum
+// and decision matches a direct evaluation; the excess is evaluated without
+// FMA contraction (separate products and sums).  The walk for the width
+// becomes a search for the nearest positions left and right of the peak
+// with 2 e < e_max.
 struct Excess {
   double lb0, dlb, c0, cden, wlen;
   __device__ __forceinline__ int64_t operator()(double S, int64_t i) const {
@@ -333,24 +337,57 @@ struct Excess {
   }
 };
 
-__device__ __forceinline__ double window_sum(const void* counts, int dtype, int64_t off, int64_t i,
-                                             int64_t W) {
-  double s = 0.0;
-  for (int64_t q = i - W; q <= i + W; ++q) s += count_any(counts, dtype, off + q);
-  return s;
+// Calls fn(S, i) for every window position i of [q0, q1) (one wave, lane l
+// taking positions q0 + l, q0 + 64 + l, ...), S the window sum over
+// [i - W, i + W].
+template <class Fn>
+__device__ __forceinline__ void window_walk(const void* counts, int dtype, int64_t off, int64_t q0,
+                                            int64_t q1, int64_t W, Fn fn) {
+  if (q0 >= q1) return;
+  const int lane = static_cast<int>(threadIdx.x & 63u);
+  double s0 = 0.0;
+  for (int64_t q = q0 - W + lane; q <= q0 + W; q += 64) s0 += count_any(counts, dtype, off + q);
+#pragma unroll
+  for (int k = 32; k > 0; k >>= 1) s0 += __shfl_xor(s0, k);
+  double carry = s0;  // S(q0), then S of the previous step's last position
+  for (int64_t base = q0; base < q1; base += 64) {
+    const int64_t i = base + lane;
+    double d = 0.0;
+    if (i > q0 && i < q1)
+      d = count_any(counts, dtype, off + i + W) - count_any(counts, dtype, off + i - W - 1);
+#pragma unroll
+    for (int k = 1; k < 64; k <<= 1) {
+      const double u = __shfl_up(d, k);
+      if (lane >= k) d += u;
+    }
+    const double S = carry + d;
+    if (i < q1) fn(S, i);
+    carry = __shfl(S, 63);
+  }
 }
 
-__global__ __launch_bounds__(256) void k_default_starts(const void* counts, int dtype,
-                                                        const int64_t* __restrict__ offsets,
-                                                        const double* __restrict__ ranges,
-                                                        double t_shift, double t_scale,
-                                                        double* __restrict__ theta0) {
-  __shared__ double red_d[2][256];
-  __shared__ int64_t red_e[256];
-  __shared__ int64_t red_i[256];
-  __shared__ int64_t red_j[256];
+// Threads per histogram: 16 waves (a histogram of 65,536 bins walks 64
+// steps of 64 positions per wave and pass).  Measured on the 4096-histogram
+// Gauss + exponential batch: 0.89 ms with 16 waves, 0.91 ms with four, and
+// 2.86 ms when each thread walked its own segment of positions with
+// scattered loads.  Per position the background's exp and the division
+// before it now dominate; both stay, since the excess must round as the
+// direct evaluation does.
+constexpr int kDsThreads = 1024;
+constexpr int kDsWaves = kDsThreads / 64;
+
+__global__ __launch_bounds__(kDsThreads) void k_default_starts(const void* counts, int dtype,
+                                                               const int64_t* __restrict__ offsets,
+                                                               const double* __restrict__ ranges,
+                                                               double t_shift, double t_scale,
+                                                               double* __restrict__ theta0) {
+  __shared__ double red_d[2][kDsWaves];
+  __shared__ int64_t red_e[kDsWaves];
+  __shared__ int64_t red_i[kDsWaves];
+  __shared__ int64_t red_j[kDsWaves];
   const int b = blockIdx.x;
   const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
   const int64_t off = offsets[b];
   const int64_t nb = offsets[b + 1] - off;
   if (nb < 1) {  // empty histogram: no start (uniform over the block)
@@ -360,87 +397,98 @@ __global__ __launch_bounds__(256) void k_default_starts(const void* counts, int 
   const double lo = ranges[2 * b], hi = ranges[2 * b + 1];
   const double h = (hi - lo) / static_cast<double>(nb);
   const int64_t ne = nb / 25 > 0 ? nb / 25 : 1;  // 4% of the bins at each edge
-  // edge sums
+  // edge sums (integer-valued: exact in any order)
   double sl = 0.0, sr = 0.0;
-  for (int64_t i = t; i < ne; i += 256) {
+  for (int64_t i = t; i < ne; i += kDsThreads) {
     sl += count_any(counts, dtype, off + i);
     sr += count_any(counts, dtype, off + nb - ne + i);
   }
-  red_d[0][t] = sl;
-  red_d[1][t] = sr;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      red_d[0][t] += red_d[0][t + w];
-      red_d[1][t] += red_d[1][t + w];
-    }
-    __syncthreads();
+#pragma unroll
+  for (int k = 32; k > 0; k >>= 1) {
+    sl += __shfl_xor(sl, k);
+    sr += __shfl_xor(sr, k);
   }
-  const double bk0 = fmax(red_d[0][0] / static_cast<double>(ne), 1.0);
-  const double bk1 = fmax(red_d[1][0] / static_cast<double>(ne), 1.0);
+  if (lane == 0) {
+    red_d[0][wv] = sl;
+    red_d[1][wv] = sr;
+  }
+  __syncthreads();
+  double esl = 0.0, esr = 0.0;
+#pragma unroll
+  for (int w = 0; w < kDsWaves; ++w) {
+    esl += red_d[0][w];
+    esr += red_d[1][w];
+  }
+  const double bk0 = fmax(esl / static_cast<double>(ne), 1.0);
+  const double bk1 = fmax(esr / static_cast<double>(ne), 1.0);
   const double c0 = 0.5 * static_cast<double>(ne);
   const double c1 = static_cast<double>(nb) - 0.5 * static_cast<double>(ne);
   const int64_t W = nb / 256 > 1 ? nb / 256 : 1;
   const double lb0 = log(bk0);
   const Excess ex{lb0, log(bk1) - lb0, c0, c1 - c0, static_cast<double>(2 * W + 1)};
-  // this thread's segment [p0, p1) of the window positions [W, nb - W)
+  // this wave's range [q0, q1) of the window positions [W, nb - W)
   const int64_t nv = nb - 2 * W > 0 ? nb - 2 * W : 0;
-  const int64_t L = (nv + 255) / 256;
-  const int64_t p0 = W + t * L;
-  const int64_t p1 = (W + (t + 1) * L < nb - W) ? W + (t + 1) * L : nb - W;
-  // pass 1: largest excess, first position
+  const int64_t Lw = (nv + kDsWaves - 1) / kDsWaves;
+  const int64_t q0 = W + wv * Lw;
+  const int64_t q1 = (W + (wv + 1) * Lw < nb - W) ? W + (wv + 1) * Lw : nb - W;
+  // pass 1: largest excess, first position (per lane, positions increase)
   int64_t be = INT64_MIN, bi = 0;
-  if (p0 < p1) {
-    double S = window_sum(counts, dtype, off, p0, W);
-    for (int64_t i = p0;; ++i) {
-      const int64_t e = ex(S, i);
-      if (e > be) {
-        be = e;
-        bi = i;
-      }
-      if (i + 1 >= p1) break;
-      S += count_any(counts, dtype, off + i + W + 1) - count_any(counts, dtype, off + i - W);
+  window_walk(counts, dtype, off, q0, q1, W, [&](double S, int64_t i) {
+    const int64_t e = ex(S, i);
+    if (e > be) {
+      be = e;
+      bi = i;
+    }
+  });
+  // the largest excess, the first position among equals: over the lanes,
+  // then over the waves
+#pragma unroll
+  for (int k = 32; k > 0; k >>= 1) {
+    const int64_t oe = __shfl_xor(be, k), oi = __shfl_xor(bi, k);
+    if (oe > be || (oe == be && oi < bi)) {
+      be = oe;
+      bi = oi;
     }
   }
-  red_e[t] = be;
-  red_i[t] = bi;
-  __syncthreads();
-  if (t == 0) {
-    int64_t e = INT64_MIN, idx = nb / 2;
-    for (int q = 0; q < 256; ++q)  // segments in position order: first max wins
-      if (red_e[q] > e) {
-        e = red_e[q];
-        idx = red_i[q];
-      }
-    if (e == INT64_MIN) {  // histogram shorter than one window
-      e = 0;
-      idx = nb / 2;
-    }
-    red_e[0] = e;
-    red_i[0] = idx;
+  if (lane == 0) {
+    red_e[wv] = be;
+    red_i[wv] = bi;
   }
   __syncthreads();
-  const int64_t emax = red_e[0], imax = red_i[0];
+  int64_t emax = INT64_MIN, imax = nb / 2;
+#pragma unroll
+  for (int w = 0; w < kDsWaves; ++w)
+    if (red_e[w] > emax || (red_e[w] == emax && red_i[w] < imax)) {
+      emax = red_e[w];
+      imax = red_i[w];
+    }
+  if (emax == INT64_MIN) {  // histogram shorter than one window
+    emax = 0;
+    imax = nb / 2;
+  }
   __syncthreads();
   // pass 2: nearest positions left / right of the peak with 2 e < emax
   int64_t pl = INT64_MIN, pr = INT64_MAX;
-  if (p0 < p1 && (p0 < imax || p1 - 1 > imax)) {
-    double S = window_sum(counts, dtype, off, p0, W);
-    for (int64_t i = p0;; ++i) {
-      if (i != imax && 2 * ex(S, i) < emax) {
-        if (i < imax) pl = i;                 // keeps the largest below the peak
-        else if (pr == INT64_MAX) pr = i;     // first above the peak
-      }
-      if (i + 1 >= p1 || (i > imax && pr != INT64_MAX)) break;
-      S += count_any(counts, dtype, off + i + W + 1) - count_any(counts, dtype, off + i - W);
+  window_walk(counts, dtype, off, q0, q1, W, [&](double S, int64_t i) {
+    if (i != imax && 2 * ex(S, i) < emax) {
+      if (i < imax) pl = i > pl ? i : pl;  // the largest below the peak
+      else pr = i < pr ? i : pr;           // the smallest above it
     }
+  });
+#pragma unroll
+  for (int k = 32; k > 0; k >>= 1) {
+    const int64_t ol = __shfl_xor(pl, k), orr = __shfl_xor(pr, k);
+    pl = ol > pl ? ol : pl;
+    pr = orr < pr ? orr : pr;
   }
-  red_e[t] = pl;
-  red_j[t] = pr;
+  if (lane == 0) {
+    red_e[wv] = pl;
+    red_j[wv] = pr;
+  }
   __syncthreads();
   if (t == 0) {
     int64_t l = INT64_MIN, r = INT64_MAX;
-    for (int q = 0; q < 256; ++q) {
+    for (int q = 0; q < kDsWaves; ++q) {
       l = red_e[q] > l ? red_e[q] : l;
       r = red_j[q] < r ? red_j[q] : r;
     }
@@ -471,7 +519,7 @@ __global__ __launch_bounds__(256) void k_default_starts(const void* counts, int 
 hipError_t default_starts(int B, const void* counts, int dtype, const int64_t* offsets,
                           const double* ranges, double t_shift, double t_scale, double* theta0,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_default_starts, dim3(B), dim3(256), 0, s, counts, dtype, offsets, ranges,
+  hipLaunchKernelGGL(k_default_starts, dim3(B), dim3(kDsThreads), 0, s, counts, dtype, offsets, ranges,
                      t_shift, t_scale, theta0);
   return hipGetLastError();
 }
